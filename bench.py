@@ -1,0 +1,279 @@
+"""Benchmark: subgraphs laid out per second, batched vs plain, on one MI355X.
+
+Workload (default): 4096 independent stochastic-block-model subgraphs, sizes
+log-uniform in [32, 2048], 4-16 blocks each, p_in = 0.2, p_out = 0.01, unit
+weights; per subgraph all-pairs PPR (alpha = 0.15, L1 residual 1e-6, T = 86
+pushes), DPPR, PDist and 200 Jacobi stress-layout sweeps from U[-1,1]^2.
+
+A step is one pass of the whole path over the batch: one replay of the HIP
+graph that holds planning, the persistent PPR kernel, PDist and the 200
+layout launches.  The plain path runs the same subgraphs one at a time
+through the C ABI (ppr_matrix, pdist, 200 x layout_step per subgraph).
+
+Prints one JSON line.  Inputs are synthetic and seeded; they are generated
+and uploaded before the timed region.
+"""
+import argparse
+import ctypes as C
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+ALPHA = 0.15
+TOL = 1e-6
+STRESS_ITERS = 200
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {
+    "batch_ppr_kernel": ["paper_2112_14944_amd/csrc/ppr_core.hpp", "paper_2112_14944_amd/csrc/batch.hip"],
+    "batch_layout_kernel": ["paper_2112_14944_amd/csrc/layout_core.hpp", "paper_2112_14944_amd/csrc/batch.hip"],
+}
+
+
+def traffic_from_profiles(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(f"{kernel}@{workload}")
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != source_hash(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(graphs, sample_count=8):
+    """The FP64 oracle (unchanged) on a stratified sample of the batch: the
+    subgraphs at evenly spaced size quantiles, each through all-pairs PPR,
+    PDist and 200 Jacobi sweeps.  Returns subgraphs/s on this host."""
+    import oracle as O
+    import synth
+
+    sizes = np.array([g.n for g in graphs])
+    order = np.argsort(sizes, kind="stable")
+    qs = (np.arange(sample_count) + 0.5) / sample_count
+    pick = order[np.minimum((qs * len(order)).astype(int), len(order) - 1)]
+    t0 = time.perf_counter()
+    for gi in pick:
+        g = graphs[gi]
+        W = O.weight_matrix(g.n, g.eu, g.ev)
+        d = O.degrees(W)
+        src = np.arange(g.n)
+        est, _, _ = O.ppr_power_iteration(O.transition(W), src, ALPHA, tol=TOL)
+        D = O.pdist(O.dppr(est, d, src), g.n)
+        X = synth.uniform_layout(g.n, int(gi)).astype(np.float64)
+        for _ in range(STRESS_ITERS):
+            X = O.jacobi_step(X, D)
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    return dict(value=len(pick) / dt, unit="subgraphs/s", cores=int(threads), kind="oracle",
+                sample=f"{len(pick)} subgraphs at evenly spaced size quantiles (n={sorted(int(sizes[i]) for i in pick)}), "
+                       f"all-pairs PPR T=86 + PDist + {STRESS_ITERS} FP64 Jacobi sweeps, {dt:.1f} s",
+                seconds=dt, host_cpus=len(os.sched_getaffinity(0)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--graphs", type=int, default=4096)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the stage-timing pass")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1 "
+                                   "(the multi-GPU sharding is a design, not a build)"}))
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2112_14944_amd import _lib as L
+    from paper_2112_14944_amd import ops
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    G = args.graphs
+    t0 = time.perf_counter()
+    graphs = synth.sbm_batch(G, seed=synth.BASE_SEED)
+    gb = synth.concat_graphs(graphs)
+    sizes = gb.sizes
+    log(f"generated {G} subgraphs in {time.perf_counter() - t0:.1f}s: nodes={int(sizes.sum())} "
+        f"arcs={gb.col_idx.shape[0]} sum n^2={int((sizes ** 2).sum())}")
+    b = ops.Batch(gb, dev)
+    x0 = torch.as_tensor(synth.uniform_layout(b.n_nodes, synth.BASE_SEED + 99), device=dev)
+    bufs = b.buffers(x0)
+    T, _ = ops.pushes_for_tolerance(ALPHA, TOL, 100000)
+    plan = ops.BatchPlan(b, bufs, alpha=ALPHA, tol=TOL, stress_iters=STRESS_ITERS)
+    stream = torch.cuda.current_stream()
+    for i in range(args.warmup):
+        plan.launch()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.launch()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    value = G / (ms_step / 1e3)
+    log(f"batched: {ms_step:.2f} ms/step -> {value:.1f} subgraphs/s (wall {wall:.2f}s for {args.steps} steps)")
+    stress = bufs["stress"].cpu().numpy()
+    assert np.all(np.isfinite(stress)), "non-finite stress in the batched result"
+
+    # ---- per-stage timing (HIP events recorded by the library on this stream)
+    stages = None
+    roof = None
+    n64 = sizes.astype(np.float64)
+    nnz = np.diff(gb.row_ptr.astype(np.int64))
+    arcs_per_graph = np.add.reduceat(nnz, gb.node_off[:-1].astype(np.int64)) if len(nnz) else np.zeros(G)
+    ppr_flops = float(((T - 1) * arcs_per_graph * n64).sum())   # one add per (arc, source) per push
+    layout_bytes = float((4.0 * n64 * n64 + 16.0 * n64).sum())  # Delta once + X in/out per sweep
+    if not args.no_profile:
+        bufs_p = b.buffers(x0)
+        ms = ops.pprviz_batch_profile(b, bufs_p, alpha=ALPHA, tol=TOL, stress_iters=STRESS_ITERS)
+        assert torch.equal(bufs_p["x_out"], bufs["x_out"]), "profiled run differs from the graph replay"
+        del bufs_p
+        ppr_ms, layout_ms = ms[1], ms[3]
+        lay_launch_ms = layout_ms / (STRESS_ITERS + 1)
+        st_ppr = dict(kernel="batch_ppr_kernel", ms=ppr_ms, launches=1, bound="alu", unit="TFLOP/s",
+                      achieved=ppr_flops / (ppr_ms * 1e-3) / 1e12, peak=PEAK_FP32_TFLOPS,
+                      work=f"{ppr_flops:.4g} FP32 adds (one per arc, source and push)")
+        st_ppr["frac"] = st_ppr["achieved"] / PEAK_FP32_TFLOPS
+        st_lay = dict(kernel="batch_layout_kernel", ms=layout_ms, launches=STRESS_ITERS + 1, bound="hbm",
+                      unit="GB/s", achieved=layout_bytes / (lay_launch_ms * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
+                      work=f"{layout_bytes:.4g} B per sweep (Delta read once, X in and out)")
+        st_lay["frac"] = st_lay["achieved"] / PEAK_HBM_GBS
+        stages = dict(plan_ms=ms[0], ppr=st_ppr, pdist_ms=ms[2], layout=st_lay)
+        dom = st_ppr if ppr_ms >= layout_ms else st_lay
+        traffic = traffic_from_profiles(dom["kernel"], f"sbm_batch_{G}")
+        roof = dict(kernel=dom["kernel"], bound=dom["bound"], achieved=dom["achieved"], peak=dom["peak"],
+                    unit=dom["unit"], frac=dom["frac"], traffic=traffic)
+        log(f"stages ms: plan {ms[0]:.2f} ppr {ppr_ms:.2f} pdist {ms[2]:.2f} layout {layout_ms:.2f}; "
+            f"ppr {st_ppr['achieved']:.2f} TFLOP/s, layout {st_lay['achieved']:.0f} GB/s")
+
+    # ---- plain path: one subgraph at a time through the C ABI
+    plain = None
+    if not args.no_plain:
+        lib = L.lib()
+        sp = C.c_void_p(stream.cuda_stream)
+        per = []
+        max_n = int(sizes.max())
+        ws_layout = torch.empty(lib.layout_workspace(max_n), dtype=torch.uint8, device=dev)
+        csrs = []
+        for g in graphs:
+            csr = ops.Csr.from_graph(g, dev)
+            cg = csr.c()
+            src = torch.arange(g.n, dtype=torch.int32, device=dev)
+            wsz = lib.ppr_matrix_workspace(C.byref(cg), g.n, g.n)
+            ws = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
+            dppr = torch.empty((g.n, g.n), dtype=torch.float32, device=dev)
+            delta = torch.empty_like(dppr)
+            xa = torch.empty((g.n, 2), dtype=torch.float32, device=dev)
+            xb = torch.empty_like(xa)
+            csrs.append((csr, cg, src, ws, dppr, delta, xa, xb))
+        a0 = gb.node_off
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        pe0 = torch.cuda.Event(enable_timing=True)
+        pe1 = torch.cuda.Event(enable_timing=True)
+        pe0.record(stream)
+        it = C.c_int32()
+        for gi, (csr, cg, src, ws, dppr, delta, xa, xb) in enumerate(csrs):
+            n = graphs[gi].n
+            st = lib.ppr_matrix(C.byref(cg), C.c_void_p(src.data_ptr()), n, None, n, ALPHA, TOL, 100000, None,
+                                C.c_void_p(dppr.data_ptr()), None, C.byref(it), C.c_void_p(ws.data_ptr()),
+                                ws.numel(), sp)
+            assert st == 0
+            assert lib.pdist(C.c_void_p(dppr.data_ptr()), n, n, C.c_void_p(delta.data_ptr()), sp) == 0
+            xa.copy_(x0[int(a0[gi]):int(a0[gi + 1])])
+            pd, pa, pb = C.c_void_p(delta.data_ptr()), C.c_void_p(xa.data_ptr()), C.c_void_p(xb.data_ptr())
+            wsl = C.c_void_p(ws_layout.data_ptr())
+            for s in range(STRESS_ITERS):
+                lib.layout_step(pd, n, pa, pb, None, wsl, ws_layout.numel(), sp)
+                pa, pb = pb, pa
+        pe1.record(stream)
+        torch.cuda.synchronize()
+        plain_wall = time.perf_counter() - p0
+        plain_ms = pe0.elapsed_time(pe1)
+        # same results as the batched path
+        gi = int(np.argmax(sizes))
+        res = csrs[gi][6] if STRESS_ITERS % 2 == 0 else csrs[gi][7]
+        same = torch.equal(res, bufs["x_out"][int(a0[gi]):int(a0[gi + 1])])
+        plain = dict(value=G / (plain_ms / 1e3), unit="subgraphs/s", ms=plain_ms, wall_s=plain_wall,
+                     launches_per_subgraph=2 + STRESS_ITERS + 1, same_result_as_batched=bool(same))
+        log(f"plain: {plain_ms:.1f} ms -> {plain['value']:.1f} subgraphs/s; batched/plain = "
+            f"{value / plain['value']:.2f}x; identical={same}")
+        del csrs
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a sample ...")
+        cpu = cpu_baseline(graphs)
+        log(f"oracle: {cpu['value']:.4f} subgraphs/s ({cpu['seconds']:.1f}s, {cpu['cores']} threads)")
+
+    out = {
+        "metric": "subgraphs laid out/sec (batched vs plain, same GPU) at PPR err<=1e-6; SpMM HBM GB/s",
+        "value": value,
+        "unit": "subgraphs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded SBM subgraphs; no dataset)",
+        "config": {"workload": f"sbm_batch_{G}: {G} SBM subgraphs, n log-uniform [32,2048], 4-16 blocks, "
+                               f"p_in 0.2, p_out 0.01; all-pairs PPR alpha 0.15 to L1 1e-6 (T={T}), PDist, "
+                               f"{STRESS_ITERS} Jacobi stress sweeps; one HIP-graph replay per step",
+                   "subgraphs": G, "nodes": int(sizes.sum()), "pairs": int((sizes ** 2).sum()),
+                   "pushes": T, "stress_iters": STRESS_ITERS},
+        "plain": plain,
+        "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "roofline": roof,
+        "stages": stages,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

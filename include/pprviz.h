@@ -1,0 +1,281 @@
+/*
+ * pprviz.h - C ABI of the MI355X (gfx950) PPR -> DPPR -> PDist -> stress
+ * layout library.
+ *
+ * Paper: "Effective and Efficient PageRank-based Positioning for Graph
+ * Visualization" (arXiv 2112.14944).  Each entry point names the passage that
+ * defines what it computes.
+ *
+ * Conventions for every call
+ *  - Every array argument is a DEVICE pointer owned by the caller, unless the
+ *    argument is documented as a host pointer.  The library never allocates or
+ *    frees device memory: scratch space comes from a caller-provided workspace
+ *    whose size is given by the matching *_workspace() query.
+ *  - Matrices are dense, row-major, FP32, with the leading dimension equal to
+ *    their column count unless stated otherwise.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    asynchronously in stream order.  Argument validation happens on the host
+ *    before anything is enqueued; a call that returns an error enqueues nothing.
+ *  - Graphs are undirected: the CSR holds both arcs u->v and v->u of every
+ *    edge, each arc carries the weight of its edge (weights must be finite and
+ *    > 0), row_ptr/col_idx are int32, there are no self-loops or duplicate
+ *    arcs.  A node without arcs behaves as if it had a self-loop, so each walk
+ *    step stays stochastic (the paper leaves dangling nodes open; this only
+ *    affects pi(v, v) of an isolated v).
+ *  - The walk's restart probability alpha must lie in (0, 1).
+ *  - No C++ exception crosses this boundary.  Thread safety: calls that share
+ *    no output or workspace buffers may run concurrently; the library keeps no
+ *    mutable global state.
+ */
+#ifndef PPRVIZ_H
+#define PPRVIZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PPR_OK = 0,
+    PPR_EINVAL = -1,      /* bad size, NULL pointer, alpha outside (0,1), ... */
+    PPR_ENOCONV = -2,     /* max_iter reached before the residual tolerance; outputs are still written */
+    PPR_EWORKSPACE = -3,  /* workspace NULL or smaller than the *_workspace() query */
+    PPR_EHIP = -4,        /* a HIP runtime call failed (including an earlier asynchronous error) */
+    PPR_ENONFINITE = -5,  /* a checked result was NaN or Inf (e.g. from non-finite weights) */
+    PPR_EUNSUPPORTED = -6 /* the size exceeds what this build handles (see each call) */
+} ppr_status;
+
+/* Undirected graph in symmetric CSR form (see conventions above). */
+typedef struct {
+    int32_t n;               /* node count, >= 1 */
+    int64_t nnz;             /* arc count = 2 x edge count, < 2^31 */
+    const int32_t* row_ptr;  /* device int32[n+1], row_ptr[0] = 0, row_ptr[n] = nnz */
+    const int32_t* col_idx;  /* device int32[nnz], arcs of node v at [row_ptr[v], row_ptr[v+1]) */
+    const float* weight;     /* device float[nnz] arc weights, or NULL for unit weights */
+} ppr_csr;
+
+/* Library version string (static storage). */
+const char* pprviz_version(void);
+
+/* Human-readable text for a status code (static storage). */
+const char* pprviz_status_string(int status);
+
+/*
+ * Number of pushes T the power iteration performs for a given L1 residual
+ * tolerance (host-only, no GPU work).
+ *
+ * Section 3.3 computes near-exact PPR by power iteration until the error is
+ * small; the paper's push (Section 3.3, Eq. eq:fwd-invariant) moves alpha of
+ * every residue into the estimate and spreads the rest over out-neighbours,
+ * so with a stochastic walk the residue's L1 norm after t synchronous pushes
+ * is exactly (1-alpha)^t and bounds the L1 error of each PPR row.  T is the
+ * smallest t with (1-alpha)^t <= tol, capped at max_iter; tol <= 0 means
+ * T = max_iter.  *converged is set to 1 when the cap was not needed.
+ * Returns PPR_EINVAL for alpha outside (0,1), max_iter < 0 or NULL outputs.
+ */
+ppr_status pprviz_pushes_for_tolerance(float alpha, double tol, int32_t max_iter,
+                                       int32_t* pushes, int32_t* converged);
+
+/* ------------------------------------------------------------------------
+ * Multi-source personalized PageRank (Section 3.1) and DPPR (Definition
+ * def:pprdist), by synchronous push / power iteration (Section 3.3).
+ * ---------------------------------------------------------------------- */
+
+/* Workspace bytes needed by ppr_matrix for this graph and source count. */
+size_t ppr_matrix_workspace(const ppr_csr* g, int32_t n_src, int32_t n_tgt);
+
+/*
+ * pi_hat(s, t) after T pushes from every source s in src[0..n_src), for the
+ * targets t in tgt[0..n_tgt) (tgt == NULL: all nodes, n_tgt must equal n).
+ *
+ *  ppr_out   float[n_src * n_tgt] or NULL: ppr_out[i*n_tgt + j] = pi_hat(src[i], tgt[j])
+ *  dppr_out  float[n_src * n_tgt] or NULL: d(src[i]) * pi_hat(src[i], tgt[j]),
+ *            the degree-normalized PPR of Definition def:pprdist, d = weighted
+ *            out-degree (sum of the node's arc weights).
+ *  T is chosen by pprviz_pushes_for_tolerance(alpha, tol_l1, max_iter).
+ *  resid_out HOST double[n_src] or NULL.  When non-NULL the call synchronizes
+ *            `stream` and returns, per source, the FP64 L1 norm of the remaining
+ *            residue, 1 - sum over ALL nodes v of pi_hat(src[i], v), computed
+ *            in FP64 from the FP32 estimates; a non-finite value makes the call
+ *            return PPR_ENONFINITE.  When NULL nothing is synchronized.
+ *  iters_out HOST int32 or NULL: receives T.
+ * Sources must be distinct valid node ids.  Precision: FP32 arithmetic,
+ * FP64 for the residual check.  Returns PPR_ENOCONV (outputs still written)
+ * when max_iter capped T before the tolerance was met.
+ */
+ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src,
+                      const int32_t* tgt, int32_t n_tgt, float alpha, double tol_l1,
+                      int32_t max_iter, float* ppr_out, float* dppr_out,
+                      double* resid_out, int32_t* iters_out,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * PDist (Definition def:pprdist, Eq. eq:pprdist)
+ * ---------------------------------------------------------------------- */
+
+/*
+ * delta[i*k + j] = min(max(1 - ln z, 2), 2 ln n_clamp), z = dppr[i][j] + dppr[j][i],
+ * natural logarithm; z <= 0 (an unreachable pair) gives 2 ln n_clamp; the
+ * diagonal is written as 0.  dppr is a k x k DPPR block whose rows (sources)
+ * and columns (targets) index the same k nodes in the same order.  n_clamp is
+ * the node count n of the graph the PPR ran on (the n of Eq. eq:pprdist).
+ * delta may not alias dppr.
+ */
+ppr_status pdist(const float* dppr, int32_t k, int64_t n_clamp, float* delta, void* stream);
+
+/*
+ * Gradient of a scalar loss through pdist.  grad_delta holds dLoss/dDelta for
+ * each unordered pair, stored symmetric (both [i][j] and [j][i] hold it, as
+ * stress_backward writes it).  Writes grad_dppr[i][j] = grad_dppr[j][i] =
+ * grad_delta[i][j] * dDelta/dz, with dDelta/dz = -1/z strictly inside the
+ * clamp range of Eq. eq:pprdist and 0 on or beyond its kinks; diagonal 0.
+ */
+ppr_status pdist_backward(const float* dppr, const float* grad_delta, int32_t k,
+                          int64_t n_clamp, float* grad_dppr, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Stress layout (Section 5, Eq. eq:loss; appendix "Stress Majorization")
+ * ---------------------------------------------------------------------- */
+
+/* Workspace bytes for layout_step / stress_eval on k nodes. */
+size_t layout_workspace(int32_t k);
+
+/*
+ * Stress L(X | Delta) = sum_{i<j} (1 - ||X_i - X_j|| / Delta_ij)^2 of Eq.
+ * eq:loss.  delta: symmetric k x k, positive off the diagonal (diagonal
+ * ignored).  x: float[k*2] (x, y per node).  stress_out: DEVICE double[1],
+ * written asynchronously (FP32 pair terms, FP64 accumulation).
+ */
+ppr_status stress_eval(const float* delta, int32_t k, const float* x, double* stress_out,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * One Jacobi sweep of the stress-majorization system L^w X = L^Y Y of the
+ * appendix, from X = Y = x_in:
+ *   x_out_i = sum_{j!=i} w_ij (Y_j + Delta_ij (Y_i - Y_j)/||Y_i - Y_j||) / sum_{j!=i} w_ij,
+ *   w_ij = Delta_ij^-2,
+ * where a coincident pair (Y_i == Y_j) contributes w_ij Y_j and no direction
+ * term (L^Y is zero there).  Same fixed points as the exact update
+ * X = (L^w)^-1 L^Y Y; O(k^2) per step, no linear solve.
+ * x_out must not alias x_in.  stress_out: DEVICE double[1] or NULL, receives
+ * L(x_in | Delta).
+ */
+ppr_status layout_step(const float* delta, int32_t k, const float* x_in, float* x_out,
+                       double* stress_out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Gradient of grad_scale * L(X | Delta) (Eq. eq:loss):
+ *   grad_x[i]  = grad_scale * sum_{j!=i} 2 w_ij (d_ij - Delta_ij)(X_i - X_j)/d_ij
+ *                (= 2 (L^w X - L^X X)_i in the appendix notation; coincident
+ *                pairs contribute 0),  float[k*2] or NULL;
+ *   grad_delta = grad_scale * dL/dDelta_ij for each unordered pair i != j,
+ *                2 (1 - d_ij/Delta_ij) d_ij / Delta_ij^2, stored symmetric,
+ *                diagonal 0,  float[k*k] or NULL.
+ */
+ppr_status stress_backward(const float* delta, int32_t k, const float* x, float grad_scale,
+                           float* grad_x, float* grad_delta, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Edge-weight gradient through all-pairs PPR (chain rule through Section
+ * 3.1's walk and Definition def:pprdist)
+ * ---------------------------------------------------------------------- */
+
+/* Workspace bytes for ppr_matrix_backward (recompute = ppr argument NULL). */
+size_t ppr_backward_workspace(const ppr_csr* g, int recompute);
+
+/*
+ * Given grad_dppr = dLoss/dpi_d for ALL pairs (n x n, rows = sources, as
+ * pdist_backward writes it), returns dLoss/dw for every arc of g:
+ *   Gb = D grad_dppr                 (pi_d = D pi_hat)
+ *   A  = sum_{j<T} ((1-alpha) P^T)^j Gb  (adjoint of pi = alpha (I-(1-alpha)P)^-1,
+ *                                      truncated like the T-push forward)
+ *   dQ[u][v] = <A[u,:], pi_hat[v,:]>
+ *   grad_arc(u->v) = (1-alpha)/d_u (dQ[u][v] - sum_b P_ub dQ[u][b])
+ *                    + sum_t grad_dppr[u][t] pi_hat[u][t]
+ * Each edge has one weight shared by its two arcs, so grad_arc[e] receives
+ * the gradient of the edge behind arc e: g(u->v) + g(v->u) (both arcs of an
+ * edge hold the same value).  Requires col_idx sorted within each row.
+ * ppr: the n x n all-pairs pi_hat (rows = sources) of the same T, or NULL to
+ * recompute it inside the workspace.  grad_arc: float[nnz].
+ * Only meaningful for graphs whose arcs each carry their own weight
+ * parameter; unit-weight graphs (weight == NULL) are differentiated at w = 1.
+ */
+ppr_status ppr_matrix_backward(const ppr_csr* g, float alpha, int32_t T, const float* ppr,
+                               const float* grad_dppr, float* grad_arc,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched path: many independent subgraphs (standing in for the supernodes
+ * of the multi-level hierarchy, Section 2.2), each taken through all-pairs
+ * PPR -> DPPR -> PDist -> stress_iters Jacobi layout steps.
+ * ---------------------------------------------------------------------- */
+
+/* Disjoint union of n_graphs unit-weight undirected subgraphs. */
+typedef struct {
+    int32_t n_graphs;
+    int64_t n_nodes;         /* total node count */
+    int64_t nnz;             /* total arc count, < 2^31 */
+    int32_t max_n;           /* largest subgraph (host-known) */
+    const int64_t* node_off; /* device int64[n_graphs+1]; graph g owns nodes [node_off[g], node_off[g+1]) */
+    const int32_t* row_ptr;  /* device int32[n_nodes+1], global CSR over the union */
+    const int32_t* col_idx;  /* device int32[nnz], global node ids (arcs never leave their subgraph) */
+    const int64_t* mat_off;  /* device int64[n_graphs+1], prefix sums of n_g^2 (dense pool offsets) */
+} ppr_batch;
+
+/* Largest subgraph the batched path accepts (all-pairs PPR kept on chip). */
+int32_t pprviz_batch_max_n(void);
+
+/* Workspace bytes for pprviz_batch / pprviz_batch_plan_create. */
+size_t pprviz_batch_workspace(const ppr_batch* b);
+
+/*
+ * For every subgraph g (n_g nodes, every node a source):
+ *   dppr_pool[mat_off[g] + i*n_g + j] = d(i) pi_hat(i, j)   (T pushes, T from tol/max_iter)
+ *   delta_pool[mat_off[g] + i*n_g + j] = PDist with n_clamp = n_g
+ *   x_out[2*node] = layout after stress_iters Jacobi sweeps from x0
+ *   stress_out[g] = L(x_out_g | Delta_g) (DEVICE double[n_graphs], or NULL)
+ * dppr_pool, delta_pool: device float[mat_off[n_graphs]].  x0, x_out: device
+ * float[2*n_nodes], must not alias.  Every subgraph must have n_g in
+ * [1, pprviz_batch_max_n()] (else PPR_EUNSUPPORTED).  Enqueues kernels on
+ * `stream` without any host synchronization.
+ */
+ppr_status pprviz_batch(const ppr_batch* b, float alpha, double tol_l1, int32_t max_iter,
+                        int32_t stress_iters, const float* x0, float* x_out,
+                        float* dppr_pool, float* delta_pool, double* stress_out,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * pprviz_batch, run once with HIP events recorded between its stages on
+ * `stream`; synchronizes the stream and writes the elapsed milliseconds of
+ * each stage to the HOST array stage_ms[4]: [0] degrees and planning,
+ * [1] all-pairs PPR of every subgraph, [2] PDist, [3] the stress_iters
+ * layout sweeps plus the final stress pass.  For measurement.
+ */
+ppr_status pprviz_batch_profile(const ppr_batch* b, float alpha, double tol_l1, int32_t max_iter,
+                                int32_t stress_iters, const float* x0, float* x_out,
+                                float* dppr_pool, float* delta_pool, double* stress_out,
+                                void* ws, size_t ws_bytes, void* stream, double* stage_ms);
+
+/*
+ * The same work captured once into a HIP graph, so that it replays as one
+ * launch.  The plan records the pointers it was created with; every buffer
+ * must stay valid until pprviz_batch_plan_destroy.  Creation enqueues nothing
+ * and does not run the work.
+ */
+typedef struct pprviz_batch_plan pprviz_batch_plan;
+
+ppr_status pprviz_batch_plan_create(const ppr_batch* b, float alpha, double tol_l1,
+                                    int32_t max_iter, int32_t stress_iters, const float* x0,
+                                    float* x_out, float* dppr_pool, float* delta_pool,
+                                    double* stress_out, void* ws, size_t ws_bytes,
+                                    void* stream, pprviz_batch_plan** plan);
+ppr_status pprviz_batch_plan_launch(pprviz_batch_plan* plan, void* stream);
+void pprviz_batch_plan_destroy(pprviz_batch_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPRVIZ_H */

@@ -147,19 +147,23 @@ def dppr(ppr_rows, d, sources):
     return ppr_rows * np.asarray(d)[sources][:, None]
 
 
-def pdist(pi_d, n_clamp):
-    """PDist matrix of Eq. eq:pprdist on a square DPPR block whose rows and
-    columns index the same node set:
-        z = pi_d[i, j] + pi_d[j, i];  Delta = min(max(1 - ln z, 2), 2 ln n).
-    Natural logarithm (Section 3.1 rationale).  z = 0 (unreachable pair) maps
-    to the upper bound 2 ln n.  The diagonal is set to 0; the stress of
-    Eq. eq:loss never reads it."""
-    pi_d = np.asarray(pi_d, dtype=np.float64)
-    z = pi_d + pi_d.T
+def pdist_of_z(z, n_clamp):
+    """Eq. eq:pprdist applied elementwise to z = pi_d(i,j) + pi_d(j,i):
+    min(max(1 - ln z, 2), 2 ln n), natural logarithm (Section 3.1
+    rationale); z = 0 (an unreachable pair) maps to the upper bound 2 ln n."""
+    z = np.asarray(z, dtype=np.float64)
     hi = 2.0 * math.log(n_clamp)
     with np.errstate(divide="ignore"):
         raw = np.where(z > 0, 1.0 - np.log(np.where(z > 0, z, 1.0)), np.inf)
-    D = np.minimum(np.maximum(raw, 2.0), hi)
+    return np.minimum(np.maximum(raw, 2.0), hi)
+
+
+def pdist(pi_d, n_clamp):
+    """PDist matrix of Eq. eq:pprdist on a square DPPR block whose rows and
+    columns index the same node set, z = pi_d[i, j] + pi_d[j, i].  The
+    diagonal is set to 0; the stress of Eq. eq:loss never reads it."""
+    pi_d = np.asarray(pi_d, dtype=np.float64)
+    D = pdist_of_z(pi_d + pi_d.T, n_clamp)
     np.fill_diagonal(D, 0.0)
     return D
 

@@ -1,0 +1,474 @@
+// Batched path: thousands of independent subgraphs (standing in for the
+// supernodes of the paper's multi-level hierarchy, Section 2.2) each taken
+// through all-pairs PPR -> DPPR -> PDist -> Jacobi stress layout, with no
+// host round trip.  Planning happens on the device, so the whole sequence can
+// be captured into one HIP graph.
+//
+//  plan      one block: counting sort of the subgraphs by size (largest first,
+//            the longest-processing-time order), per-subgraph prefix sums of
+//            PPR tiles, PDist tiles and layout row blocks.
+//  ppr       persistent kernel, one 1024-thread block per CU; blocks pop
+//            (subgraph, source tile) tasks from an atomic counter in LPT order
+//            and run the LDS-resident power iteration of ppr_core.hpp.
+//  pdist     grid-stride over (subgraph, 64x64 tile) items.
+//  layout    stress_iters launches, each grid-stride over (subgraph, 16-row
+//            block) items; then one stress pass of the final layout.
+#include <math.h>
+
+#include <algorithm>
+
+#include "internal.hpp"
+#include "layout_core.hpp"
+#include "ppr_core.hpp"
+
+namespace pprviz {
+
+constexpr int kBatchMaxN = Res<16>::NMAX;  // 2304
+constexpr int kPlanThreads = 1024;
+
+struct BatchPlan {
+    int32_t* order;      // [G] subgraph ids, largest first
+    int64_t* tile_pre;   // [G+1] prefix of PPR tiles in LPT order
+    int64_t* pd_pre;     // [G+1] prefix of 64x64 PDist tiles (subgraph order)
+    int64_t* rb_pre;     // [G+1] prefix of 16-row layout blocks (subgraph order)
+    int32_t* counter;    // [1] PPR task queue head
+};
+
+__device__ __forceinline__ int graph_n(const int64_t* node_off, int g) {
+    return (int)(node_off[g + 1] - node_off[g]);
+}
+
+// Largest i with pre[i] <= item, for a non-decreasing prefix array of size m+1.
+__device__ __forceinline__ int find_segment(const int64_t* __restrict__ pre, int m, int64_t item) {
+    int lo = 0, hi = m - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// PPR tiles of an n-node subgraph (0 for a size the resident kernel cannot
+// hold; the host rejects such batches before launch).
+__device__ __forceinline__ int64_t tiles_of(int n) {
+    const int cols = res_cols_for(n);
+    return cols == 0 ? 0 : (n + cols - 1) / cols;
+}
+
+__global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t* __restrict__ node_off, int32_t G,
+                                                                  BatchPlan p) {
+    __shared__ int32_t hist[kBatchMaxN + 2];
+    __shared__ int64_t scan_tmp[kPlanThreads];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kBatchMaxN + 2; i += kPlanThreads) hist[i] = 0;
+    __syncthreads();
+    for (int g = tid; g < G; g += kPlanThreads) atomicAdd(&hist[min(graph_n(node_off, g), kBatchMaxN + 1)], 1);
+    __syncthreads();
+    // exclusive prefix over sizes in descending order: start[size]
+    if (tid == 0) {
+        int32_t run = 0;
+        for (int sz = kBatchMaxN + 1; sz >= 0; --sz) {
+            const int32_t c = hist[sz];
+            hist[sz] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int g = tid; g < G; g += kPlanThreads) {
+        const int pos = atomicAdd(&hist[min(graph_n(node_off, g), kBatchMaxN + 1)], 1);
+        p.order[pos] = g;
+    }
+    __syncthreads();
+    __threadfence_block();
+    // three prefix sums (sequential chunks per thread, then a block scan)
+    for (int which = 0; which < 3; ++which) {
+        int64_t* out = which == 0 ? p.tile_pre : (which == 1 ? p.pd_pre : p.rb_pre);
+        const int per = (G + kPlanThreads - 1) / kPlanThreads;
+        const int a = tid * per, b = min(G, a + per);
+        int64_t loc = 0;
+        for (int i = a; i < b; ++i) {
+            const int g = which == 0 ? p.order[i] : i;
+            const int n = graph_n(node_off, g);
+            loc += which == 0 ? tiles_of(n) : (which == 1 ? (int64_t)((n + 63) / 64) * ((n + 63) / 64)
+                                                          : (int64_t)((n + kLayoutRowsPerBlock - 1) / kLayoutRowsPerBlock));
+        }
+        scan_tmp[tid] = loc;
+        __syncthreads();
+        if (tid == 0) {
+            int64_t run = 0;
+            for (int i = 0; i < kPlanThreads; ++i) {
+                const int64_t c = scan_tmp[i];
+                scan_tmp[i] = run;
+                run += c;
+            }
+        }
+        __syncthreads();
+        int64_t run = scan_tmp[tid];
+        for (int i = a; i < b; ++i) {
+            out[i] = run;
+            const int g = which == 0 ? p.order[i] : i;
+            const int n = graph_n(node_off, g);
+            run += which == 0 ? tiles_of(n) : (which == 1 ? (int64_t)((n + 63) / 64) * ((n + 63) / 64)
+                                                          : (int64_t)((n + kLayoutRowsPerBlock - 1) / kLayoutRowsPerBlock));
+        }
+        if (tid == kPlanThreads - 1) out[G] = run;
+        __syncthreads();
+    }
+    if (tid == 0) p.counter[0] = 0;
+}
+
+struct BatchArgs {
+    const int64_t* node_off;
+    const int64_t* mat_off;
+    int32_t G;
+    ResArgs r;  // graph-global fields; src/tgt null (all pairs), ppr_out null
+};
+
+__global__ __launch_bounds__(kResThreads) void batch_ppr_kernel(BatchArgs b, BatchPlan p) {
+    __shared__ ResLds L;
+    __shared__ int32_t task_sh;
+    const int64_t total = p.tile_pre[b.G];
+    for (;;) {
+        if (threadIdx.x == 0) task_sh = atomicAdd(p.counter, 1);
+        __syncthreads();
+        const int64_t task = __builtin_amdgcn_readfirstlane(task_sh);
+        __syncthreads();
+        if (task >= total) return;
+        const int pos = find_segment(p.tile_pre, b.G, task);
+        const int g = p.order[pos];
+        const int64_t tile = task - p.tile_pre[pos];
+        const int n = graph_n(b.node_off, g);
+        const int cols = res_cols_for(n);
+        TileTask t;
+        t.n = n;
+        t.s0 = (int)(tile * cols);
+        t.ncols = min(cols, n - t.s0);
+        t.n_tgt = n;
+        t.base = b.node_off[g];
+        t.out_off = b.mat_off[g];
+        t.ld = n;
+        if (cols == 64) res_tile<64, false>(t, b.r, L);
+        else if (cols == 32) res_tile<32, false>(t, b.r, L);
+        else res_tile<16, false>(t, b.r, L);
+    }
+}
+
+__global__ __launch_bounds__(256) void batch_pdist_kernel(const int64_t* __restrict__ node_off,
+                                                          const int64_t* __restrict__ mat_off, int32_t G,
+                                                          const int64_t* __restrict__ pd_pre,
+                                                          const float* __restrict__ pid, float* __restrict__ delta) {
+    __shared__ float tt[64][65];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int64_t total = pd_pre[G];
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const int g = find_segment(pd_pre, G, item);
+        const int k = graph_n(node_off, g);
+        const int nt = (k + 63) / 64;
+        const int64_t local = item - pd_pre[g];
+        const int64_t i0 = (local / nt) * 64, j0 = (local % nt) * 64;
+        const float* P = pid + mat_off[g];
+        float* D = delta + mat_off[g];
+        const float hi = pdist_hi(k);
+        __syncthreads();
+        for (int jj = w; jj < 64; jj += 4) {
+            const int64_t j = j0 + jj, i = i0 + lane;
+            tt[jj][lane] = (j < k && i < k) ? P[j * k + i] : 0.f;
+        }
+        __syncthreads();
+        for (int ii = w; ii < 64; ii += 4) {
+            const int64_t i = i0 + ii, j = j0 + lane;
+            if (i >= k || j >= k) continue;
+            const float z = P[i * k + j] + tt[lane][ii];
+            D[i * k + j] = (i == j) ? 0.f : pdist_value(z, hi);
+        }
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void batch_layout_kernel(const int64_t* __restrict__ node_off,
+                                                           const int64_t* __restrict__ mat_off, int32_t G,
+                                                           const int64_t* __restrict__ rb_pre,
+                                                           const float* __restrict__ delta,
+                                                           const float2* __restrict__ x, float2* __restrict__ xout,
+                                                           double* __restrict__ part) {
+    __shared__ double red[4];
+    const int wave = threadIdx.x >> 6;
+    const int64_t total = rb_pre[G];
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const int g = find_segment(rb_pre, G, item);
+        const int k = graph_n(node_off, g);
+        const int64_t rb = item - rb_pre[g];
+        const int64_t nb = node_off[g];
+        const int row_begin = (int)(rb * kLayoutRowsPerBlock) + wave * kLayoutRowsPerWave;
+        const double st = layout_rows<MODE>(delta + mat_off[g], k, k, x + nb, row_begin,
+                                            xout ? xout + nb : nullptr, 1.f, nullptr, nullptr);
+        if (MODE == kLayoutStress) {
+            if ((threadIdx.x & 63) == 0) red[wave] = st;
+            __syncthreads();
+            if (threadIdx.x == 0) part[item] = (red[0] + red[1]) + (red[2] + red[3]);
+            __syncthreads();
+        }
+    }
+}
+
+// stress_out[g] = sum of its row-block partials, in order.
+__global__ void batch_stress_sum_kernel(const int64_t* __restrict__ rb_pre, int32_t G, const double* __restrict__ part,
+                                        double* __restrict__ out) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    double s = 0.0;
+    for (int64_t i = rb_pre[g]; i < rb_pre[g + 1]; ++i) s += part[i];
+    out[g] = s;
+}
+
+__global__ void copy_kernel(const float* __restrict__ a, float* __restrict__ b, int64_t count) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) b[i] = a[i];
+}
+
+struct BatchWs {
+    float* deg;
+    float* invd;
+    float* xtmp;
+    double* part;
+    BatchPlan plan;
+};
+
+template <typename Cursor>
+static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
+    BatchWs t;
+    t.deg = c.template take<float>((size_t)b->n_nodes);
+    t.invd = c.template take<float>((size_t)b->n_nodes);
+    t.xtmp = c.template take<float>((size_t)b->n_nodes * 2);
+    // row blocks: sum over g of ceil(n_g/16) <= n_nodes/16 + G
+    t.part = c.template take<double>((size_t)(b->n_nodes / kLayoutRowsPerBlock + b->n_graphs + 1));
+    t.plan.order = c.template take<int32_t>((size_t)b->n_graphs);
+    t.plan.tile_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
+    t.plan.pd_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
+    t.plan.rb_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
+    t.plan.counter = c.template take<int32_t>(64);
+    if (w) *w = t;
+}
+
+static int device_cu_count() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+    return cus;
+}
+
+static ppr_status batch_validate(const ppr_batch* b, float alpha, int32_t max_iter, int32_t stress_iters,
+                                 const float* x0, float* x_out, float* dppr_pool, float* delta_pool) {
+    if (b == nullptr || b->n_graphs < 1 || b->n_nodes < 1 || b->nnz < 0 || b->nnz >= (int64_t)INT32_MAX)
+        return PPR_EINVAL;
+    if (!b->node_off || !b->row_ptr || (b->nnz > 0 && !b->col_idx) || !b->mat_off) return PPR_EINVAL;
+    if (!(alpha > 0.0f && alpha < 1.0f) || max_iter < 0 || stress_iters < 0) return PPR_EINVAL;
+    if (!x0 || !x_out || x0 == x_out || !dppr_pool || !delta_pool) return PPR_EINVAL;
+    if (b->max_n < 1) return PPR_EINVAL;
+    if (b->max_n > kBatchMaxN) return PPR_EUNSUPPORTED;
+    return PPR_OK;
+}
+
+// Enqueues the batched pipeline.  With `ev` (5 events) the stage boundaries
+// are recorded: [0] start, [1] after planning, [2] after PPR, [3] after PDist,
+// [4] after the layout sweeps and the final stress pass.
+static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int32_t stress_iters, const float* x0,
+                                float* x_out, float* dppr_pool, float* delta_pool, double* stress_out,
+                                const BatchWs& w, hipStream_t s, hipEvent_t* ev = nullptr) {
+    const int G = b->n_graphs;
+    if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[0], s));
+    launch_degree(b->row_ptr, nullptr, b->n_nodes, w.deg, w.invd, s);
+    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, b->node_off, G, w.plan);
+    if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[1], s));
+
+    BatchArgs ba;
+    ba.node_off = b->node_off;
+    ba.mat_off = b->mat_off;
+    ba.G = G;
+    ba.r.row_ptr = b->row_ptr;
+    ba.r.col_idx = b->col_idx;
+    ba.r.weight = nullptr;
+    ba.r.invd = w.invd;
+    ba.r.deg = w.deg;
+    ba.r.src = nullptr;
+    ba.r.tgt = nullptr;
+    ba.r.alpha = alpha;
+    ba.r.T = T;
+    ba.r.ppr_out = nullptr;
+    ba.r.dppr_out = dppr_pool;
+    ba.r.resid = nullptr;
+    const int cus = device_cu_count();
+    hipLaunchKernelGGL(batch_ppr_kernel, dim3(cus), dim3(kResThreads), 0, s, ba, w.plan);
+    if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[2], s));
+
+    const unsigned grid = (unsigned)cus * 8;
+    hipLaunchKernelGGL(batch_pdist_kernel, dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off, G, w.plan.pd_pre,
+                       dppr_pool, delta_pool);
+    if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[3], s));
+
+    // Jacobi sweeps, ping-pong so that the last one lands in x_out.
+    const float2* cur = reinterpret_cast<const float2*>(x0);
+    float2* bufs[2] = {reinterpret_cast<float2*>(x_out), reinterpret_cast<float2*>(w.xtmp)};
+    int next = (stress_iters % 2 == 1) ? 0 : 1;
+    if (stress_iters == 0) {
+        hipLaunchKernelGGL(copy_kernel, dim3(1024), dim3(256), 0, s, x0, x_out, b->n_nodes * 2);
+        cur = reinterpret_cast<const float2*>(x_out);
+    }
+    for (int it = 0; it < stress_iters; ++it) {
+        float2* out = bufs[next];
+        hipLaunchKernelGGL((batch_layout_kernel<kLayoutStep>), dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off, G,
+                           w.plan.rb_pre, delta_pool, cur, out, nullptr);
+        cur = out;
+        next ^= 1;
+    }
+    if (stress_out) {
+        hipLaunchKernelGGL((batch_layout_kernel<kLayoutStress>), dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off,
+                           G, w.plan.rb_pre, delta_pool, cur, nullptr, w.part);
+        hipLaunchKernelGGL(batch_stress_sum_kernel, dim3((G + 255) / 256), dim3(256), 0, s, w.plan.rb_pre, G, w.part,
+                           stress_out);
+    }
+    if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[4], s));
+    return launch_status();
+}
+
+}  // namespace pprviz
+
+using namespace pprviz;
+
+struct pprviz_batch_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int32_t pprviz_batch_max_n(void) { return kBatchMaxN; }
+
+size_t pprviz_batch_workspace(const ppr_batch* b) {
+    if (b == nullptr || b->n_graphs < 1 || b->n_nodes < 1) return 0;
+    WsSize c;
+    batch_layout_ws(c, b, nullptr);
+    return c.used;
+}
+
+ppr_status pprviz_batch(const ppr_batch* b, float alpha, double tol_l1, int32_t max_iter, int32_t stress_iters,
+                        const float* x0, float* x_out, float* dppr_pool, float* delta_pool, double* stress_out,
+                        void* ws, size_t ws_bytes, void* stream) {
+    ppr_status st = batch_validate(b, alpha, max_iter, stress_iters, x0, x_out, dppr_pool, delta_pool);
+    if (st != PPR_OK) return st;
+    int32_t T = 0, conv = 1;
+    st = pprviz_pushes_for_tolerance(alpha, tol_l1, max_iter, &T, &conv);
+    if (st != PPR_OK) return st;
+    WsCursor cur{static_cast<char*>(ws), ws_bytes};
+    BatchWs w;
+    batch_layout_ws(cur, b, &w);
+    if (ws == nullptr || cur.used > ws_bytes) return PPR_EWORKSPACE;
+    if (pending_error() != PPR_OK) return PPR_EHIP;
+    st = batch_enqueue(b, alpha, T, stress_iters, x0, x_out, dppr_pool, delta_pool, stress_out, w,
+                       static_cast<hipStream_t>(stream));
+    if (st != PPR_OK) return st;
+    return conv ? PPR_OK : PPR_ENOCONV;
+}
+
+ppr_status pprviz_batch_profile(const ppr_batch* b, float alpha, double tol_l1, int32_t max_iter,
+                                int32_t stress_iters, const float* x0, float* x_out, float* dppr_pool,
+                                float* delta_pool, double* stress_out, void* ws, size_t ws_bytes, void* stream,
+                                double* stage_ms) {
+    if (stage_ms == nullptr) return PPR_EINVAL;
+    ppr_status st = batch_validate(b, alpha, max_iter, stress_iters, x0, x_out, dppr_pool, delta_pool);
+    if (st != PPR_OK) return st;
+    int32_t T = 0, conv = 1;
+    st = pprviz_pushes_for_tolerance(alpha, tol_l1, max_iter, &T, &conv);
+    if (st != PPR_OK) return st;
+    WsCursor cur{static_cast<char*>(ws), ws_bytes};
+    BatchWs w;
+    batch_layout_ws(cur, b, &w);
+    if (ws == nullptr || cur.used > ws_bytes) return PPR_EWORKSPACE;
+    if (pending_error() != PPR_OK) return PPR_EHIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t ev[5] = {};
+    for (int i = 0; i < 5; ++i) {
+        if (hipEventCreate(&ev[i]) != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
+            return PPR_EHIP;
+        }
+    }
+    st = batch_enqueue(b, alpha, T, stress_iters, x0, x_out, dppr_pool, delta_pool, stress_out, w, s, ev);
+    if (st == PPR_OK && hipEventSynchronize(ev[4]) != hipSuccess) st = PPR_EHIP;
+    if (st == PPR_OK) {
+        for (int i = 0; i < 4; ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) st = PPR_EHIP;
+            stage_ms[i] = ms;
+        }
+    }
+    for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+    if (st != PPR_OK) return st;
+    return conv ? PPR_OK : PPR_ENOCONV;
+}
+
+ppr_status pprviz_batch_plan_create(const ppr_batch* b, float alpha, double tol_l1, int32_t max_iter,
+                                    int32_t stress_iters, const float* x0, float* x_out, float* dppr_pool,
+                                    float* delta_pool, double* stress_out, void* ws, size_t ws_bytes, void* stream,
+                                    pprviz_batch_plan** plan) {
+    (void)stream;
+    if (plan == nullptr) return PPR_EINVAL;
+    *plan = nullptr;
+    ppr_status st = batch_validate(b, alpha, max_iter, stress_iters, x0, x_out, dppr_pool, delta_pool);
+    if (st != PPR_OK) return st;
+    int32_t T = 0, conv = 1;
+    st = pprviz_pushes_for_tolerance(alpha, tol_l1, max_iter, &T, &conv);
+    if (st != PPR_OK) return st;
+    WsCursor cur{static_cast<char*>(ws), ws_bytes};
+    BatchWs w;
+    batch_layout_ws(cur, b, &w);
+    if (ws == nullptr || cur.used > ws_bytes) return PPR_EWORKSPACE;
+    if (pending_error() != PPR_OK) return PPR_EHIP;
+    hipStream_t cs = nullptr;
+    PPRVIZ_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = batch_enqueue(b, alpha, T, stress_iters, x0, x_out, dppr_pool, delta_pool, stress_out, w, cs);
+        e = hipStreamEndCapture(cs, &graph);
+    }
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess || st != PPR_OK || graph == nullptr) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st != PPR_OK ? st : PPR_EHIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return PPR_EHIP;
+    }
+    auto* p = new (std::nothrow) pprviz_batch_plan;
+    if (p == nullptr) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return PPR_EHIP;
+    }
+    p->graph = graph;
+    p->exec = exec;
+    *plan = p;
+    return conv ? PPR_OK : PPR_ENOCONV;
+}
+
+ppr_status pprviz_batch_plan_launch(pprviz_batch_plan* plan, void* stream) {
+    if (plan == nullptr || plan->exec == nullptr) return PPR_EINVAL;
+    if (pending_error() != PPR_OK) return PPR_EHIP;
+    PPRVIZ_HIP_TRY(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)));
+    return PPR_OK;
+}
+
+void pprviz_batch_plan_destroy(pprviz_batch_plan* plan) {
+    if (plan == nullptr) return;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
+}
+
+}  // extern "C"

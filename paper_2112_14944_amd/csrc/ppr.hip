@@ -1,0 +1,246 @@
+// Single-graph multi-source PPR / DPPR (ppr_matrix) and shared helpers.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "ppr_core.hpp"
+#include "ppr_stream.hpp"
+#include "internal.hpp"
+
+namespace pprviz {
+
+__global__ void degree_kernel(const int32_t* __restrict__ row_ptr, const float* __restrict__ weight,
+                              int64_t n, float* __restrict__ deg, float* __restrict__ invd) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int rs = row_ptr[v], re = row_ptr[v + 1];
+    float d;
+    if (weight) {
+        float s = 0.f;
+        for (int e = rs; e < re; ++e) s += weight[e];
+        d = s;
+    } else {
+        d = (float)(re - rs);
+    }
+    deg[v] = d;
+    invd[v] = (re > rs && d > 0.f) ? 1.0f / d : 1.0f;
+}
+
+template <int COLS, bool WEIGHTED>
+__global__ __launch_bounds__(kResThreads) void ppr_resident_kernel(ResArgs a, int32_t n, int32_t n_src,
+                                                                 int32_t n_tgt) {
+    __shared__ ResLds L;
+    TileTask t;
+    t.n = n;
+    t.s0 = blockIdx.x * COLS;
+    t.ncols = min(COLS, n_src - t.s0);
+    t.n_tgt = n_tgt;
+    t.base = 0;
+    t.out_off = 0;
+    t.ld = n_tgt;
+    res_tile<COLS, WEIGHTED>(t, a, L);
+}
+
+void launch_degree(const int32_t* row_ptr, const float* weight, int64_t n, float* deg, float* invd,
+                   hipStream_t s) {
+    int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(degree_kernel, dim3((unsigned)blocks), dim3(256), 0, s, row_ptr, weight, n, deg, invd);
+}
+
+template <int COLS>
+static void launch_resident(bool weighted, const ResArgs& a, int n, int n_src, int n_tgt, hipStream_t s) {
+    dim3 grid((n_src + COLS - 1) / COLS);
+    if (weighted)
+        hipLaunchKernelGGL((ppr_resident_kernel<COLS, true>), grid, dim3(kResThreads), 0, s, a, n, n_src, n_tgt);
+    else
+        hipLaunchKernelGGL((ppr_resident_kernel<COLS, false>), grid, dim3(kResThreads), 0, s, a, n, n_src, n_tgt);
+}
+
+// Workspace layout of ppr_matrix.
+struct PprWs {
+    float* deg;
+    float* invd;
+    double* resid;
+    float* ya;
+    float* yb;
+    double* part;
+};
+
+ppr_status validate_csr(const ppr_csr* g) {
+    if (g == nullptr || g->n < 1 || g->nnz < 0 || g->nnz >= (int64_t)INT32_MAX) return PPR_EINVAL;
+    if (g->row_ptr == nullptr || (g->nnz > 0 && g->col_idx == nullptr)) return PPR_EINVAL;
+    return PPR_OK;
+}
+
+bool use_resident(int n) { return res_cols_for(n) != 0; }
+
+// T pushes from every source; deg/invd must already hold the degrees.  The
+// stream-path buffers (ya, yb, part) are only touched when n is too large for
+// the LDS-resident kernel.
+void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int32_t* tgt, int32_t n_tgt,
+                 float alpha, int32_t T, float* ppr_out, float* dppr_out, const float* deg, const float* invd,
+                 double* resid, float* ya, float* yb, double* part, hipStream_t s) {
+    const int n = g->n;
+    if (use_resident(n)) {
+        ResArgs a;
+        a.row_ptr = g->row_ptr;
+        a.col_idx = g->col_idx;
+        a.weight = g->weight;
+        a.invd = invd;
+        a.deg = deg;
+        a.src = src;
+        a.tgt = tgt;
+        a.alpha = alpha;
+        a.T = T;
+        a.ppr_out = ppr_out;
+        a.dppr_out = dppr_out;
+        a.resid = resid;
+        const bool wt = g->weight != nullptr;
+        switch (res_cols_for(n)) {
+            case 64: launch_resident<64>(wt, a, n, n_src, n_tgt, s); break;
+            case 32: launch_resident<32>(wt, a, n, n_src, n_tgt, s); break;
+            default: launch_resident<16>(wt, a, n, n_src, n_tgt, s); break;
+        }
+    } else {
+        StreamArgs sa;
+        sa.row_ptr = g->row_ptr;
+        sa.col_idx = g->col_idx;
+        sa.weight = g->weight;
+        sa.invd = invd;
+        sa.deg = deg;
+        sa.n = n;
+        sa.ncols = n_src;
+        sa.ld = stream_ld(n_src);
+        sa.alpha = alpha;
+        sa.src = src;
+        sa.forcing = nullptr;
+        sa.ld_forcing = 0;
+        const float* x = stream_power_iteration(sa, T, ya, yb, s);
+        stream_write_outputs(x, sa, tgt, n_tgt, ppr_out, dppr_out, s);
+        if (resid) stream_residuals(x, sa, part, resid, s);
+    }
+}
+
+template <typename Cursor>
+static void ppr_ws_layout(Cursor& c, int n, int n_src, PprWs* w) {
+    auto* deg = c.template take<float>(n);
+    auto* invd = c.template take<float>(n);
+    auto* resid = c.template take<double>(std::max(n_src, 1));
+    if (w) {
+        w->deg = deg;
+        w->invd = invd;
+        w->resid = resid;
+        w->ya = w->yb = nullptr;
+        w->part = nullptr;
+    }
+    if (!use_resident(n)) {
+        const int64_t ldy = stream_ld(n_src);
+        auto* ya = c.template take<float>((size_t)n * ldy);
+        auto* yb = c.template take<float>((size_t)n * ldy);
+        auto* part = c.template take<double>((size_t)stream_resid_chunks(n) * ldy);
+        if (w) {
+            w->ya = ya;
+            w->yb = yb;
+            w->part = part;
+        }
+    }
+}
+
+}  // namespace pprviz
+
+using namespace pprviz;
+
+extern "C" {
+
+const char* pprviz_version(void) { return "pprviz-gfx950 1.0"; }
+
+const char* pprviz_status_string(int status) {
+    switch (status) {
+        case PPR_OK: return "ok";
+        case PPR_EINVAL: return "invalid argument";
+        case PPR_ENOCONV: return "iteration cap reached before the residual tolerance";
+        case PPR_EWORKSPACE: return "workspace missing or too small";
+        case PPR_EHIP: return "HIP runtime error";
+        case PPR_ENONFINITE: return "non-finite result";
+        case PPR_EUNSUPPORTED: return "size not supported by this build";
+        default: return "unknown status";
+    }
+}
+
+ppr_status pprviz_pushes_for_tolerance(float alpha, double tol, int32_t max_iter, int32_t* pushes,
+                                       int32_t* converged) {
+    if (!(alpha > 0.0f && alpha < 1.0f) || max_iter < 0 || pushes == nullptr) return PPR_EINVAL;
+    const double q = 1.0 - (double)alpha;
+    int32_t T;
+    int32_t conv = 1;
+    if (!(tol > 0.0)) {
+        T = max_iter;
+    } else if (tol >= 1.0) {
+        T = 0;
+    } else {
+        double t = ceil(log(tol) / log(q));
+        if (t < 0) t = 0;
+        if (t > 2.0e9) t = 2.0e9;
+        int64_t ti = (int64_t)t;
+        while (ti > 0 && pow(q, (double)(ti - 1)) <= tol) --ti;
+        while (pow(q, (double)ti) > tol) ++ti;
+        if (ti > max_iter) {
+            T = max_iter;
+            conv = 0;
+        } else {
+            T = (int32_t)ti;
+        }
+    }
+    *pushes = T;
+    if (converged) *converged = conv;
+    return PPR_OK;
+}
+
+
+size_t ppr_matrix_workspace(const ppr_csr* g, int32_t n_src, int32_t n_tgt) {
+    (void)n_tgt;
+    if (g == nullptr || g->n < 1 || n_src < 0) return 0;
+    WsSize c;
+    ppr_ws_layout(c, g->n, n_src, nullptr);
+    return c.used;
+}
+
+ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src, const int32_t* tgt,
+                      int32_t n_tgt, float alpha, double tol_l1, int32_t max_iter, float* ppr_out,
+                      float* dppr_out, double* resid_out, int32_t* iters_out, void* ws, size_t ws_bytes,
+                      void* stream) {
+    ppr_status st = validate_csr(g);
+    if (st != PPR_OK) return st;
+    if (n_src < 0 || n_tgt < 0 || (n_src > 0 && src == nullptr)) return PPR_EINVAL;
+    if (tgt == nullptr && n_tgt != g->n) return PPR_EINVAL;
+    if (!(alpha > 0.0f && alpha < 1.0f) || max_iter < 0) return PPR_EINVAL;
+    if ((int64_t)n_src * (int64_t)std::max(n_tgt, 1) > ((int64_t)1 << 40)) return PPR_EUNSUPPORTED;
+    int32_t T = 0, conv = 1;
+    st = pprviz_pushes_for_tolerance(alpha, tol_l1, max_iter, &T, &conv);
+    if (st != PPR_OK) return st;
+    if (iters_out) *iters_out = T;
+    if (n_src == 0) return conv ? PPR_OK : PPR_ENOCONV;
+    WsCursor cur{static_cast<char*>(ws), ws_bytes};
+    PprWs w;
+    ppr_ws_layout(cur, g->n, n_src, &w);
+    if (ws == nullptr || cur.used > ws_bytes) return PPR_EWORKSPACE;
+    if (pending_error() != PPR_OK) return PPR_EHIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int n = g->n;
+    launch_degree(g->row_ptr, g->weight, n, w.deg, w.invd, s);
+
+    ppr_forward(g, src, n_src, tgt, n_tgt, alpha, T, ppr_out, dppr_out, w.deg, w.invd, w.resid, w.ya, w.yb,
+                w.part, s);
+    st = launch_status();
+    if (st != PPR_OK) return st;
+    if (resid_out) {
+        PPRVIZ_HIP_TRY(hipMemcpyAsync(resid_out, w.resid, sizeof(double) * n_src, hipMemcpyDeviceToHost, s));
+        PPRVIZ_HIP_TRY(hipStreamSynchronize(s));
+        for (int i = 0; i < n_src; ++i)
+            if (!isfinite(resid_out[i])) return PPR_ENONFINITE;
+    }
+    return conv ? PPR_OK : PPR_ENOCONV;
+}
+
+}  // extern "C"

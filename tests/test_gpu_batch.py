@@ -1,0 +1,96 @@
+"""GPU parity of the batched path: many subgraphs in one enqueue / one HIP
+graph replay, against the plain one-subgraph-per-call path (same kernels, so
+the same bits) and against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from gpu_util import ALPHA, PDIST_REL, get_ops, oracle_ppr, rel_err
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 32, 45, 64, 100, 180, 300, 576, 577, 700, 1152, 1153, 1500, 2048, 2304]
+
+
+@pytest.fixture(scope="module")
+def setup():
+    ops = get_ops()
+    rng = np.random.default_rng(11)
+    graphs = []
+    for i, n in enumerate(SIZES):
+        nb = int(min(n, rng.integers(4, 17)))
+        graphs.append(synth.sbm(synth.equal_blocks(n, max(nb, 1)), 0.2, 0.01, 5000 + i))
+    gb = synth.concat_graphs(graphs)
+    b = ops.Batch(gb, "cuda")
+    x0 = torch.as_tensor(synth.uniform_layout(b.n_nodes, 12), device="cuda")
+    bufs = b.buffers(x0)
+    print(f"[batch] graphs={b.n_graphs} nodes={b.n_nodes} nnz={b.nnz}", flush=True)
+    ops.pprviz_batch(b, bufs, tol=1e-6, stress_iters=50)
+    torch.cuda.synchronize()
+    return ops, gb, b, bufs, x0
+
+
+def test_batch_equals_plain_path(setup):
+    ops, gb, b, bufs, x0 = setup
+    for gi, g in enumerate(gb.graphs):
+        n = g.n
+        a = int(gb.node_off[gi])
+        csr = ops.Csr.from_graph(g, "cuda")
+        _, dppr, T, _ = ops.ppr_matrix(csr, np.arange(n), tol=1e-6, want_ppr=False)
+        assert T == 86
+        bd = ops.graph_block(gb, bufs["dppr"], gi)
+        assert torch.equal(bd, dppr), f"dppr differs for graph {gi} (n={n})"
+        delta = ops.pdist(dppr, n)
+        assert torch.equal(ops.graph_block(gb, bufs["delta"], gi), delta)
+        xf = ops.layout(delta, x0[a:a + n].contiguous(), 50)
+        assert torch.equal(bufs["x_out"][a:a + n], xf), f"layout differs for graph {gi} (n={n})"
+        st = ops.stress_eval(delta, xf)
+        assert abs(bufs["stress"][gi].item() - st.item()) <= 1e-12 * max(1.0, abs(st.item()))
+
+
+def test_batch_matches_oracle(setup):
+    ops, gb, b, bufs, x0 = setup
+    for gi, g in enumerate(gb.graphs):
+        n = g.n
+        if n <= 1200:
+            src = np.arange(n)
+        else:  # big subgraphs: sampled sources (the oracle is slow there)
+            src = np.sort(np.random.default_rng(gi).choice(n, 24, replace=False))
+        est, dppr_o, T_o, _, d = oracle_ppr(g, src, tol=1e-6)
+        assert T_o == 86
+        bd = ops.graph_block(gb, bufs["dppr"], gi).double().cpu().numpy()[src]
+        errd = (np.abs(bd - dppr_o) / np.maximum(1.0, d[src])[:, None]).max()
+        assert errd <= 1e-6, (gi, n, errd)
+        D = ops.graph_block(gb, bufs["delta"], gi).double().cpu().numpy()
+        if n <= 1200:
+            D_o = O.pdist(dppr_o, n)
+            assert rel_err(D, D_o) <= PDIST_REL
+            if 2 <= n <= 300:  # 50 FP64 Jacobi steps on the oracle's own Delta
+                a = int(gb.node_off[gi])
+                X = x0[a:a + n].double().cpu().numpy()
+                for _ in range(50):
+                    X = O.jacobi_step(X, D_o)
+                s_o = O.stress(X, D_o)
+                assert abs(bufs["stress"][gi].item() - s_o) <= 1e-3 * max(s_o, 1e-12), (gi, n)
+        else:
+            D_o = O.pdist(dppr_o[:, src], n)
+            assert rel_err(D[np.ix_(src, src)], D_o) <= PDIST_REL
+
+
+def test_graph_plan_replays(setup):
+    ops, gb, b, bufs, x0 = setup
+    ref = {k: bufs[k].clone() for k in ("dppr", "delta", "x_out", "stress")}
+    bufs2 = b.buffers(x0)
+    plan = ops.BatchPlan(b, bufs2, tol=1e-6, stress_iters=50)
+    for rep in range(3):
+        for k in ("dppr", "delta", "x_out", "stress"):
+            bufs2[k].fill_(-1.0)
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(bufs2[k], ref[k]), (rep, k)
+        _ = (bufs2["x_out"] * 2).sum().item()  # eager work between replays
+    plan.close()

@@ -1,0 +1,159 @@
+"""GPU parity: multi-source PPR / DPPR / PDist / layout on single graphs,
+through the C ABI, against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from gpu_util import (ALPHA, PDIST_REL, STEP_REL, assert_ppr_close, get_ops, oracle_ppr, rel_err)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ops():
+    return get_ops()
+
+
+def _csr(ops, g):
+    return ops.Csr.from_graph(g, "cuda")
+
+
+def test_c1_erdos_renyi_all_pairs(ops):
+    # ER n=500, mean degree 8, all 500 sources, L1 residual 1e-10 (T = 142),
+    # then PDist and 300 Jacobi layout steps from U[-1,1]^2.
+    g = synth.erdos_renyi(500, 8, synth.BASE_SEED)
+    src = np.arange(g.n)
+    print(f"[c1] n={g.n} nnz={g.nnz}", flush=True)
+    ppr, dppr, T, resid = ops.ppr_matrix(_csr(ops, g), src, tol=1e-10, check_residual=True)
+    est, dppr_o, T_o, res_o, d = oracle_ppr(g, src, tol=1e-10)
+    assert T == T_o == 142
+    assert_ppr_close(ppr, dppr, est, dppr_o, d[src])
+    assert np.abs(resid - res_o).max() <= 2e-6
+    delta = ops.pdist(dppr, g.n)
+    D_o = O.pdist(dppr_o, g.n)
+    assert rel_err(delta.double().cpu().numpy(), D_o) <= PDIST_REL
+    x0 = torch.as_tensor(synth.uniform_layout(g.n, synth.BASE_SEED + 1), device="cuda")
+    # one step from the same start, then the 300-step trajectory's final stress
+    x1, s0 = ops.layout_step(delta, x0, with_stress=True)
+    X0 = x0.double().cpu().numpy()
+    assert abs(s0.item() - O.stress(X0, D_o)) <= 1e-5 * O.stress(X0, D_o)
+    assert rel_err(x1.double().cpu().numpy(), O.jacobi_step(X0, D_o)) <= STEP_REL
+    xf = ops.layout(delta, x0, 300)
+    s_gpu = ops.stress_eval(delta, xf).item()
+    Xo = X0
+    for _ in range(300):
+        Xo = O.jacobi_step(Xo, D_o)
+    s_o = O.stress(Xo, D_o)
+    assert abs(s_gpu - s_o) <= 1e-3 * s_o, (s_gpu, s_o)
+    assert s_gpu < O.stress(X0, D_o)
+
+
+def test_weighted_isolated_subsets(ops):
+    # weighted SBM with an isolated node, a ragged source subset, a shuffled
+    # target subset, fixed T (tol <= 0)
+    n = 300
+    g0 = synth.sbm(synth.equal_blocks(n, 5), 0.12, 0.01, 77, weighted=(0.5, 2.0, 78))
+    keep = (g0.eu != 7) & (g0.ev != 7)
+    g = synth.build_graph(n, g0.eu[keep], g0.ev[keep], g0.weight[keep])
+    rng = np.random.default_rng(5)
+    src = np.sort(rng.choice(n, 77, replace=False))
+    src[3] = 7  # the isolated node is a source too
+    src = np.unique(src)
+    tgt = rng.permutation(n)
+    tgt = np.concatenate([[7], tgt[tgt != 7]])[:123]  # shuffled, holds the isolated node
+    tgt = np.roll(tgt, 40)
+    ppr, dppr, T, resid = ops.ppr_matrix(_csr(ops, g), src, tgt=tgt, tol=0.0, max_iter=60, check_residual=True)
+    est, dppr_o, T_o, res_o, d = oracle_ppr(g, src, T=60)
+    assert T == 60
+    assert_ppr_close(ppr, dppr, est[:, tgt], dppr_o[:, tgt], d[src])
+    assert np.abs(resid - res_o).max() <= 2e-6
+    i7 = int(np.nonzero(src == 7)[0][0])
+    # isolated source keeps its mass: pi(7,7) = 1 - (1-alpha)^T
+    assert abs(ppr[i7].cpu().numpy()[tgt == 7].item() - (1 - (1 - ALPHA) ** 60)) <= 1e-6
+
+
+@pytest.mark.parametrize("n", [576, 577, 1152, 1153, 2304, 2305, 3001])
+def test_tile_width_boundaries_and_stream_path(ops, n):
+    # 64/32/16-column resident tiles switch at 576/1152/2304; above 2304 the
+    # iterate streams through HBM.
+    g = synth.erdos_renyi(n, 10, 1000 + n)
+    src = synth.random_sources(g, 70, 2000 + n)
+    ppr, dppr, T, resid = ops.ppr_matrix(_csr(ops, g), src, tol=1e-6, check_residual=True)
+    est, dppr_o, T_o, res_o, d = oracle_ppr(g, src, tol=1e-6)
+    assert T == T_o == 86
+    assert_ppr_close(ppr, dppr, est, dppr_o, d[src])
+    assert np.abs(resid - res_o).max() <= 2e-6
+
+
+def test_degenerate_cases(ops):
+    # single isolated node; two-node path (closed form 1/(2 - alpha)); T = 0; T = 1; no sources
+    g1 = synth.build_graph(1, [], [])
+    ppr, dppr, T, _ = ops.ppr_matrix(_csr(ops, g1), [0], tol=1e-6)
+    assert abs(ppr.item() - (1 - (1 - ALPHA) ** T)) < 1e-6 and dppr.item() == 0.0
+    g2 = synth.build_graph(2, [0], [1])
+    ppr, dppr, T, _ = ops.ppr_matrix(_csr(ops, g2), [0, 1], tol=1e-12)
+    assert abs(ppr[0, 0].item() - 1 / (2 - ALPHA)) < 1e-6
+    assert abs(ppr[1, 0].item() - (1 - ALPHA) / (2 - ALPHA)) < 1e-6
+    g = synth.erdos_renyi(40, 4, 9)
+    p0, _, T0, _ = ops.ppr_matrix(_csr(ops, g), [1, 2], tol=2.0)
+    assert T0 == 0 and p0.abs().max().item() == 0.0
+    p1, _, T1, _ = ops.ppr_matrix(_csr(ops, g), [1, 2], tol=0.0, max_iter=1)
+    assert T1 == 1 and abs(p1[0, 1].item() - ALPHA) < 1e-7 and abs(p1.sum().item() - 2 * ALPHA) < 1e-6
+    pe, _, _, _ = ops.ppr_matrix(_csr(ops, g), np.zeros(0, dtype=np.int32), tol=1e-6)
+    assert pe.shape == (0, 40)
+    # iteration cap before the tolerance: ENOCONV, outputs still written
+    from paper_2112_14944_amd._lib import PprvizError
+    with pytest.raises(PprvizError):
+        ops.ppr_matrix(_csr(ops, g), [1], tol=1e-9, max_iter=5)
+    pc, _, Tc, _ = ops.ppr_matrix(_csr(ops, g), [1], tol=1e-9, max_iter=5, allow_noconv=True)
+    est, _, _, _, _ = oracle_ppr(g, [1], T=5)
+    assert Tc == 5 and np.abs(pc.double().cpu().numpy() - est).max() <= 1e-6
+
+
+def test_nonfinite_weights_reported(ops):
+    g = synth.sbm(synth.equal_blocks(60, 3), 0.3, 0.05, 3, weighted=(0.5, 2.0, 4))
+    csr = _csr(ops, g)
+    w = csr.weight.clone()
+    w[5] = float("nan")
+    from paper_2112_14944_amd._lib import PPR_ENONFINITE, PprvizError
+    with pytest.raises(PprvizError) as ei:
+        ops.ppr_matrix(csr.with_weight(w), np.arange(60), tol=1e-6, check_residual=True)
+    assert ei.value.status == PPR_ENONFINITE
+
+
+def test_c2_chung_lu_all_pairs_sampled(ops):
+    # Chung-Lu n=20000, gamma 2.5, mean degree 20, all 20000 sources to L1
+    # residual 1e-7 (T = 100): full FP32 n x n output; the oracle checks 40
+    # sampled sources, their PDist block, and one Jacobi step of 40 sampled
+    # rows of the full-size layout.
+    g = synth.chung_lu(20000, 2.5, 20, synth.BASE_SEED + 2)
+    n = g.n
+    print(f"[c2] n={n} nnz={g.nnz}", flush=True)
+    csr = _csr(ops, g)
+    ppr, dppr, T, resid = ops.ppr_matrix(csr, np.arange(n), tol=1e-7, check_residual=True)
+    assert T == 100
+    assert np.abs(resid - (1 - ALPHA) ** 100).max() <= 2e-6
+    sample = synth.random_sources(g, 40, 31)
+    est, dppr_o, _, _, d = oracle_ppr(g, sample, tol=1e-7)
+    sidx = torch.as_tensor(sample, device="cuda").long()
+    assert_ppr_close(ppr[sidx], dppr[sidx], est, dppr_o, d[sample])
+    del ppr
+    delta = ops.pdist(dppr, n)
+    blk = delta[sidx][:, sidx].double().cpu().numpy()
+    D_blk = O.pdist(dppr_o[:, sample], n)
+    assert rel_err(blk, D_blk) <= PDIST_REL
+    # full-size layout step on sampled rows.  The oracle's Delta row i needs
+    # pi_d(j, i) for every j; for an undirected graph it equals pi_d(i, j)
+    # (reversibility, pinned in the oracle tests), so row i follows from the
+    # oracle's own PPR row of source i.
+    x0 = torch.as_tensor(synth.uniform_layout(n, 41), device="cuda")
+    x1, st = ops.layout_step(delta, x0, with_stress=True)
+    Drows = O.pdist_of_z(2.0 * dppr_o, n)
+    Drows[np.arange(len(sample)), sample] = 0.0
+    X0 = x0.double().cpu().numpy()
+    want = O.jacobi_rows(X0, Drows, sample)
+    got = x1[sidx].double().cpu().numpy()
+    assert np.abs(got - want).max() <= STEP_REL * np.abs(X0).max()
+    assert st.item() > 0 and np.isfinite(st.item())
