@@ -27,6 +27,9 @@ HIPCC_FLAGS = [
     "-Wno-unused-variable",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the resident PPR tile keeps one register per row across a step, which
+    # needs its row loop fully unrolled
+    "-mllvm", "-pragma-unroll-threshold=1000000",
 ]
 
 

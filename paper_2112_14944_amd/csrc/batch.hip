@@ -31,7 +31,8 @@ struct BatchPlan {
     int64_t* tile_pre;   // [G+1] prefix of PPR tiles in LPT order
     int64_t* pd_pre;     // [G+1] prefix of 64x64 PDist tiles (subgraph order)
     int64_t* rb_pre;     // [G+1] prefix of 16-row layout blocks (subgraph order)
-    int32_t* counter;    // [1] PPR task queue head
+    int32_t* counter;    // [3] PPR task queue heads, one per tile width
+    int32_t* cls_pos;    // [4] first LPT position of the 16-, 32- and 64-column classes, then G
 };
 
 __device__ __forceinline__ int graph_n(const int64_t* node_off, int g) {
@@ -114,7 +115,25 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t*
         if (tid == kPlanThreads - 1) out[G] = run;
         __syncthreads();
     }
-    if (tid == 0) p.counter[0] = 0;
+    // Sizes are sorted descending, so each tile width owns a contiguous range
+    // of positions: n > Res<32>::NMAX (16 columns), then n > Res<64>::NMAX
+    // (32 columns), then the rest (64 columns).
+    __shared__ int32_t cls_cnt[2];
+    if (tid < 2) cls_cnt[tid] = 0;
+    __syncthreads();
+    for (int g = tid; g < G; g += kPlanThreads) {
+        const int n = graph_n(node_off, g);
+        if (n > Res<32>::NMAX) atomicAdd(&cls_cnt[0], 1);
+        else if (n > Res<64>::NMAX) atomicAdd(&cls_cnt[1], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        p.counter[0] = p.counter[1] = p.counter[2] = 0;
+        p.cls_pos[0] = 0;
+        p.cls_pos[1] = cls_cnt[0];
+        p.cls_pos[2] = cls_cnt[0] + cls_cnt[1];
+        p.cls_pos[3] = G;
+    }
 }
 
 struct BatchArgs {
@@ -124,32 +143,36 @@ struct BatchArgs {
     ResArgs r;  // graph-global fields; src/tgt null (all pairs), ppr_out null
 };
 
+// Persistent kernel for the subgraphs of one tile width: blocks pop task ids
+// of the class's range (LPT order) until it is exhausted.
+template <int COLS, int CLS>
 __global__ __launch_bounds__(kResThreads) void batch_ppr_kernel(BatchArgs b, BatchPlan p) {
     __shared__ ResLds L;
     __shared__ int32_t task_sh;
-    const int64_t total = p.tile_pre[b.G];
+    const int p0 = p.cls_pos[CLS];
+    const int p1 = p.cls_pos[CLS + 1];
+    if (p0 >= p1) return;
+    const int64_t first = p.tile_pre[p0];
+    const int64_t last = p.tile_pre[p1];
     for (;;) {
-        if (threadIdx.x == 0) task_sh = atomicAdd(p.counter, 1);
+        if (threadIdx.x == 0) task_sh = atomicAdd(&p.counter[CLS], 1);
         __syncthreads();
-        const int64_t task = __builtin_amdgcn_readfirstlane(task_sh);
+        const int64_t task = first + __builtin_amdgcn_readfirstlane(task_sh);
         __syncthreads();
-        if (task >= total) return;
-        const int pos = find_segment(p.tile_pre, b.G, task);
+        if (task >= last) return;
+        const int pos = p0 + find_segment(p.tile_pre + p0, p1 - p0, task);
         const int g = p.order[pos];
         const int64_t tile = task - p.tile_pre[pos];
         const int n = graph_n(b.node_off, g);
-        const int cols = res_cols_for(n);
         TileTask t;
         t.n = n;
-        t.s0 = (int)(tile * cols);
-        t.ncols = min(cols, n - t.s0);
+        t.s0 = (int)(tile * COLS);
+        t.ncols = min(COLS, n - t.s0);
         t.n_tgt = n;
         t.base = b.node_off[g];
         t.out_off = b.mat_off[g];
         t.ld = n;
-        if (cols == 64) res_tile<64, false>(t, b.r, L);
-        else if (cols == 32) res_tile<32, false>(t, b.r, L);
-        else res_tile<16, false>(t, b.r, L);
+        res_tile<COLS, false>(t, b.r, L);
     }
 }
 
@@ -249,6 +272,7 @@ static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     t.plan.pd_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
     t.plan.rb_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
     t.plan.counter = c.template take<int32_t>(64);
+    t.plan.cls_pos = c.template take<int32_t>(64);
     if (w) *w = t;
 }
 
@@ -300,10 +324,12 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     ba.r.dppr_out = dppr_pool;
     ba.r.resid = nullptr;
     const int cus = device_cu_count();
-    hipLaunchKernelGGL(batch_ppr_kernel, dim3(cus), dim3(kResThreads), 0, s, ba, w.plan);
+    hipLaunchKernelGGL((batch_ppr_kernel<16, 0>), dim3(cus), dim3(kResThreads), 0, s, ba, w.plan);
+    hipLaunchKernelGGL((batch_ppr_kernel<32, 1>), dim3(cus), dim3(kResThreads), 0, s, ba, w.plan);
+    hipLaunchKernelGGL((batch_ppr_kernel<64, 2>), dim3(cus), dim3(kResThreads), 0, s, ba, w.plan);
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[2], s));
 
-    const unsigned grid = (unsigned)cus * 8;
+    const unsigned grid = (unsigned)cus * 16;
     hipLaunchKernelGGL(batch_pdist_kernel, dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off, G, w.plan.pd_pre,
                        dppr_pool, delta_pool);
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[3], s));

@@ -55,6 +55,22 @@ struct WsSize {
 
 // ---------------------------------------------------------------- device side
 
+// Pointers in the global address space.  Pointers that reach a kernel inside
+// a struct are otherwise treated as generic (flat) pointers, whose loads also
+// count against the LDS wait counter and so serialize with LDS traffic.
+template <typename T>
+using gcptr = const T __attribute__((address_space(1)))*;
+template <typename T>
+using gptr = T __attribute__((address_space(1)))*;
+template <typename T>
+__device__ __forceinline__ gcptr<T> as_global(const T* p) {
+    return (gcptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global_w(T* p) {
+    return (gptr<T>)p;
+}
+
 // Broadcast lane J of every 16-lane DPP row to the whole row (row_newbcast,
 // DPP control 0x150 + J on gfx90a and later).
 template <int J>

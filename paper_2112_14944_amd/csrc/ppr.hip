@@ -230,8 +230,8 @@ ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src, const
     const int n = g->n;
     launch_degree(g->row_ptr, g->weight, n, w.deg, w.invd, s);
 
-    ppr_forward(g, src, n_src, tgt, n_tgt, alpha, T, ppr_out, dppr_out, w.deg, w.invd, w.resid, w.ya, w.yb,
-                w.part, s);
+    ppr_forward(g, src, n_src, tgt, n_tgt, alpha, T, ppr_out, dppr_out, w.deg, w.invd, w.resid, w.ya, w.yb, w.part,
+                s);
     st = launch_status();
     if (st != PPR_OK) return st;
     if (resid_out) {

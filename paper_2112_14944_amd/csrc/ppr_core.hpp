@@ -18,20 +18,26 @@
 
 namespace pprviz {
 
-constexpr int kResThreads = 1024;
+// 512 threads (8 waves, 2 per SIMD) leave each wave 256 VGPRs.
+constexpr int kResThreads = 512;
 constexpr int kResWaves = kResThreads / kWave;
-constexpr int kResMaxK = 36;  // rows per lane held in registers across a step
+constexpr int kResMaxK = 18;  // rows per lane (4 columns each) held in registers across a step
 
+// Tile geometry.  Lanes work in quads: a quad owns 16 columns of one row, each
+// lane 4 consecutive columns read with one 16-byte LDS load per arc, and the
+// quad's arcs are broadcast inside the quad with DPP quad_perm.  A row of a
+// COLS-wide tile takes COLS/16 quads.
 template <int COLS>
 struct Res {
-    static constexpr int RPW = kWave / COLS;               // rows per wave per pass
+    static constexpr int QPR = COLS / 16;                  // quads per row
+    static constexpr int RPW = 16 / QPR;                   // rows per wave per pass
     static constexpr int RPP = kResWaves * RPW;            // rows per block pass
     static constexpr int NMAX = RPP * kResMaxK;            // largest graph for this tile width
     static constexpr int STRIDE = COLS * 4;                // bytes per LDS row
 };
 
-// LDS floats for one resident tile: (NMAX + 1 dummy zero row) * COLS, max over
-// the three tile widths (577*64, 1153*32, 2305*16).
+// LDS floats for one resident tile: n rows plus one zero row, times COLS; the
+// maximum over the three tile widths (577*64, 1153*32, 2305*16).
 constexpr int kResLdsFloats = 36928;
 static_assert((Res<64>::NMAX + 1) * 64 <= kResLdsFloats, "lds");
 static_assert((Res<32>::NMAX + 1) * 32 <= kResLdsFloats, "lds");
@@ -55,7 +61,7 @@ struct TileTask {
 struct ResArgs {
     const int32_t* row_ptr;  // global CSR row pointers
     const int32_t* col_idx;  // global node ids
-    const float* weight;     // arc weights or nullptr
+    const float* weight;     // arc weights, or nullptr
     const float* invd;       // per global node: 1/d, or 1 for a node without arcs
     const float* deg;        // per global node: weighted degree d
     const int32_t* src;      // source local ids by source index, or nullptr (source i = node i)
@@ -67,30 +73,66 @@ struct ResArgs {
     double* resid;           // nullable, indexed by source index
 };
 
-// Sum of Y[u][c] over 16 arcs whose LDS row offsets (bytes) sit in the 16
-// lanes of each DPP row; lanes past the row's end point at the zero row.
+// Broadcast lane J of every quad to the whole quad (DPP quad_perm [J,J,J,J]).
+template <int J>
+__device__ __forceinline__ int quad_bcast(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, J * 0x55, 0xf, 0xf, false);
+}
+template <int J>
+__device__ __forceinline__ float quad_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), J * 0x55, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ float4 lds_load4(const float* lds, int byte_off) {
+    return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(lds) + byte_off);
+}
+
+// One chunk of 16 arcs of a quad's row: arc m sits in lane m%4, word m/4
+// (a0..a3 hold LDS byte offsets of the neighbours' rows, a zero row past the
+// row's end).  Eight 16-byte reads are issued before their adds.
 template <bool WEIGHTED>
-__device__ __forceinline__ float gather16(const float* __restrict__ lds, int off, float w, int c4) {
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-#define PPRVIZ_G(J, ACC)                                                   \
-    {                                                                      \
-        int o = row_bcast<J>(off);                                         \
-        float x = lds_load(lds, o + c4);                                   \
-        if (WEIGHTED) ACC = fmaf(row_bcast<J>(w), x, ACC); else ACC += x; \
+__device__ __forceinline__ void gather_chunk(const float* __restrict__ lds, int a0, int a1, int a2, int a3,
+                                             float w0, float w1, float w2, float w3, int cbyte, float4& acc) {
+#define PPRVIZ_RD(M, A) y[(M) & 7] = lds_load4(lds, quad_bcast<(M) % 4>(A) + cbyte);
+#define PPRVIZ_ACC(M, W)                                          \
+    if (WEIGHTED) {                                               \
+        const float ww = quad_bcast<(M) % 4>(W);                  \
+        acc.x = fmaf(ww, y[(M) & 7].x, acc.x);                    \
+        acc.y = fmaf(ww, y[(M) & 7].y, acc.y);                    \
+        acc.z = fmaf(ww, y[(M) & 7].z, acc.z);                    \
+        acc.w = fmaf(ww, y[(M) & 7].w, acc.w);                    \
+    } else {                                                      \
+        acc.x += y[(M) & 7].x;                                    \
+        acc.y += y[(M) & 7].y;                                    \
+        acc.z += y[(M) & 7].z;                                    \
+        acc.w += y[(M) & 7].w;                                    \
     }
-    PPRVIZ_G(0, s0) PPRVIZ_G(1, s1) PPRVIZ_G(2, s2) PPRVIZ_G(3, s3)
-    PPRVIZ_G(4, s0) PPRVIZ_G(5, s1) PPRVIZ_G(6, s2) PPRVIZ_G(7, s3)
-    PPRVIZ_G(8, s0) PPRVIZ_G(9, s1) PPRVIZ_G(10, s2) PPRVIZ_G(11, s3)
-    PPRVIZ_G(12, s0) PPRVIZ_G(13, s1) PPRVIZ_G(14, s2) PPRVIZ_G(15, s3)
-#undef PPRVIZ_G
-    return (s0 + s1) + (s2 + s3);
+    float4 y[8];
+    PPRVIZ_RD(0, a0) PPRVIZ_RD(1, a0) PPRVIZ_RD(2, a0) PPRVIZ_RD(3, a0)
+    PPRVIZ_RD(4, a1) PPRVIZ_RD(5, a1) PPRVIZ_RD(6, a1) PPRVIZ_RD(7, a1)
+    __builtin_amdgcn_sched_barrier(0);
+    PPRVIZ_ACC(0, w0) PPRVIZ_ACC(1, w0) PPRVIZ_ACC(2, w0) PPRVIZ_ACC(3, w0)
+    PPRVIZ_ACC(4, w1) PPRVIZ_ACC(5, w1) PPRVIZ_ACC(6, w1) PPRVIZ_ACC(7, w1)
+    __builtin_amdgcn_sched_barrier(0);
+    PPRVIZ_RD(8, a2) PPRVIZ_RD(9, a2) PPRVIZ_RD(10, a2) PPRVIZ_RD(11, a2)
+    PPRVIZ_RD(12, a3) PPRVIZ_RD(13, a3) PPRVIZ_RD(14, a3) PPRVIZ_RD(15, a3)
+    __builtin_amdgcn_sched_barrier(0);
+    PPRVIZ_ACC(8, w2) PPRVIZ_ACC(9, w2) PPRVIZ_ACC(10, w2) PPRVIZ_ACC(11, w2)
+    PPRVIZ_ACC(12, w3) PPRVIZ_ACC(13, w3) PPRVIZ_ACC(14, w3) PPRVIZ_ACC(15, w3)
+#undef PPRVIZ_RD
+#undef PPRVIZ_ACC
 }
 
 // Keeps a value opaque to the optimizer, so that per-row loads and addresses
 // are recomputed inside each step instead of being hoisted out of the step
-// loop (where 36 rows' worth of them would no longer fit in registers).
+// loop (where 18 rows' worth of them would no longer fit in registers).
 __device__ __forceinline__ int opaque(int v) {
     asm volatile("" : "+v"(v));
+    return v;
+}
+__device__ __forceinline__ int opaque_s32(int v) {
+    v = __builtin_amdgcn_readfirstlane(v);
+    asm volatile("" : "+s"(v));
     return v;
 }
 __device__ __forceinline__ int64_t opaque_s(int64_t v) {
@@ -100,19 +142,36 @@ __device__ __forceinline__ int64_t opaque_s(int64_t v) {
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
 }
 
-// LDS of one resident tile: the iterate Y (n+1 rows of COLS floats, the last
-// row all zero) followed by the n per-node factors (1-alpha)/d.
+// LDS of one resident tile: the iterate Y (n rows of COLS floats and a zero
+// row) followed by the n per-node factors (1-alpha)/d.
 struct ResLds {
     float y[kResLdsFloats];
     float scale[Res<16>::NMAX];
 };
 
+// Loads one 16-arc chunk of a quad's row (arcs e0 + 4i + q for i = 0..3).
+template <bool WEIGHTED>
+__device__ __forceinline__ void load_chunk(gcptr<int32_t> pc, gcptr<float> pw, int e0, int re, int q, int& r0,
+                                           int& r1, int& r2, int& r3, float& w0, float& w1, float& w2,
+                                           float& w3) {
+    if (e0 + q < re) r0 = pc[e0 + q];
+    if (e0 + 4 + q < re) r1 = pc[e0 + 4 + q];
+    if (e0 + 8 + q < re) r2 = pc[e0 + 8 + q];
+    if (e0 + 12 + q < re) r3 = pc[e0 + 12 + q];
+    if (WEIGHTED) {
+        w0 = e0 + q < re ? pw[e0 + q] : 0.f;
+        w1 = e0 + 4 + q < re ? pw[e0 + 4 + q] : 0.f;
+        w2 = e0 + 8 + q < re ? pw[e0 + 8 + q] : 0.f;
+        w3 = e0 + 12 + q < re ? pw[e0 + 12 + q] : 0.f;
+    }
+}
+
 // All T pushes for one source tile with the tile's iterate resident in LDS.
-// Block = 1024 threads; lane c = lane % COLS is the tile column (source), a
-// wave covers 64/COLS rows per pass, and each lane keeps its rows' new values
-// in registers between the two barriers of a step.
+// Each lane keeps its rows' new values (4 columns per row) in registers
+// between the two barriers of a step.
 template <int COLS, bool WEIGHTED>
-__device__ void res_tile(const TileTask& t, const ResArgs& a, ResLds& L) {
+__device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, ResLds& L) {
+    constexpr int QPR = Res<COLS>::QPR;
     constexpr int RPW = Res<COLS>::RPW;
     constexpr int RPP = Res<COLS>::RPP;
     constexpr int STRIDE = Res<COLS>::STRIDE;
@@ -120,109 +179,185 @@ __device__ void res_tile(const TileTask& t, const ResArgs& a, ResLds& L) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    const int c = lane % COLS;
-    const int rsub = lane / COLS;
-    const int c4 = c * 4;
-    const int l16 = lane & 15;
+    const int quad = lane >> 2;
+    const int q = lane & 3;
+    const int rsub = quad / QPR;                 // row slot of the quad in the wave
+    const int col0 = (quad % QPR) * 16 + q * 4;  // first of the lane's 4 columns
+    const int cbyte = col0 * 4;
     const int n = t.n;
     const int64_t base = t.base;
     const float alpha = a.alpha;
     const float oma = 1.0f - alpha;
-    const int dummy = n * STRIDE;
+    const gcptr<int32_t> rp = as_global(a.row_ptr);
+    const gcptr<int32_t> pc = as_global(a.col_idx);
+    const gcptr<float> pw = as_global(a.weight);
+    const gcptr<int32_t> srcp = as_global(a.src);
 
-    int my_src = -1;
-    if (c < t.ncols) my_src = a.src ? a.src[t.s0 + c] : t.s0 + c;
+    // local source node of each of the lane's 4 columns (-1 outside the tile)
+    int msrc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = col0 + i;
+        msrc[i] = c < t.ncols ? (a.src ? srcp[t.s0 + c] : t.s0 + c) : -1;
+    }
 
     for (int i = tid; i < (n + 1) * COLS; i += kResThreads) lds[i] = 0.f;
-    for (int i = tid; i < n; i += kResThreads) L.scale[i] = oma * a.invd[base + i];
+    for (int i = tid; i < n; i += kResThreads) L.scale[i] = oma * as_global(a.invd)[base + i];
     __syncthreads();
     if (tid < t.ncols && a.T >= 2) {
-        int s = a.src ? a.src[t.s0 + tid] : t.s0 + tid;
+        int s = a.src ? srcp[t.s0 + tid] : t.s0 + tid;
         lds[s * COLS + tid] = alpha * L.scale[s];
     }
     __syncthreads();
 
-    float xr[kResMaxK];
+    float4 xr[kResMaxK];
     const int row0 = wave * RPW + rsub;  // row of pass k is row0 + k * RPP
 #pragma unroll
-    for (int k = 0; k < kResMaxK; ++k) xr[k] = (a.T >= 1 && row0 + k * RPP == my_src) ? alpha : 0.f;
+    for (int k = 0; k < kResMaxK; ++k) {
+        const int v = row0 + k * RPP;
+        const bool on = a.T >= 1;
+        xr[k] = make_float4(on && v == msrc[0] ? alpha : 0.f, on && v == msrc[1] ? alpha : 0.f,
+                            on && v == msrc[2] ? alpha : 0.f, on && v == msrc[3] ? alpha : 0.f);
+    }
 
     for (int it = 1; it < a.T; ++it) {
         const int r0 = opaque(row0);
         const int64_t b = opaque_s(base);
+        const int bi = (int)b;
+        const int n = opaque_s32(t.n);
+        const int dummy = n * STRIDE;
+        // Row-level software pipeline: the first chunk of row k+1 and the
+        // bounds of row k+2 are loaded while row k is summed.
+        int rs1 = 0, re1 = 0, rs2 = 0, re2 = 0;
+        if (r0 < n) {
+            rs1 = rp[b + r0];
+            re1 = rp[b + r0 + 1];
+        }
+        if (r0 + RPP < n) {
+            rs2 = rp[b + r0 + RPP];
+            re2 = rp[b + r0 + RPP + 1];
+        }
+        int p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+        float pw0 = 0.f, pw1 = 0.f, pw2 = 0.f, pw3 = 0.f;
+        load_chunk<WEIGHTED>(pc, pw, rs1, re1, q, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
 #pragma unroll
         for (int k = 0; k < kResMaxK; ++k) {
             if (k * RPP < n) {
                 const int v = r0 + k * RPP;
+                const int rs = rs1, re = re1;
+                const int c0 = p0, c1 = p1, c2 = p2, c3 = p3;
+                const float cw0 = pw0, cw1 = pw1, cw2 = pw2, cw3 = pw3;
+                rs1 = rs2;
+                re1 = re2;
+                if (k + 1 < kResMaxK && v + RPP < n)
+                    load_chunk<WEIGHTED>(pc, pw, rs1, re1, q, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
+                if (k + 2 < kResMaxK && v + 2 * RPP < n) {
+                    rs2 = rp[b + v + 2 * RPP];
+                    re2 = rp[b + v + 2 * RPP + 1];
+                }
                 if (v < n) {
-                    const int rs = a.row_ptr[b + v];
-                    const int re = a.row_ptr[b + v + 1];
-                    float acc = 0.f;
-                    if (rs == re) acc = lds[v * COLS + c];
-                    for (int e0 = rs; e0 < re; e0 += 16) {
-                        const int e = e0 + l16;
-                        int off = dummy;
-                        float w = 0.f;
-                        if (e < re) {
-                            off = (int)(a.col_idx[e] - b) * STRIDE;
-                            if (WEIGHTED) w = a.weight[e];
-                        }
-                        acc += gather16<WEIGHTED>(lds, off, w, c4);
+                    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (rs == re) acc = lds_load4(lds, v * STRIDE + cbyte);
+                    if (rs < re) {
+                        gather_chunk<WEIGHTED>(lds, rs + q < re ? (c0 - bi) * STRIDE : dummy,
+                                               rs + 4 + q < re ? (c1 - bi) * STRIDE : dummy,
+                                               rs + 8 + q < re ? (c2 - bi) * STRIDE : dummy,
+                                               rs + 12 + q < re ? (c3 - bi) * STRIDE : dummy, cw0, cw1, cw2, cw3,
+                                               cbyte, acc);
                     }
-                    xr[k] = acc + (v == my_src ? alpha : 0.f);
+                    // further chunks of rows longer than 16 arcs
+#pragma nounroll
+                    for (int e0 = rs + 16; e0 < re; e0 += 16) {
+                        int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+                        float dw0 = 0.f, dw1 = 0.f, dw2 = 0.f, dw3 = 0.f;
+                        load_chunk<WEIGHTED>(pc, pw, e0, re, q, d0, d1, d2, d3, dw0, dw1, dw2, dw3);
+                        gather_chunk<WEIGHTED>(lds, e0 + q < re ? (d0 - bi) * STRIDE : dummy,
+                                               e0 + 4 + q < re ? (d1 - bi) * STRIDE : dummy,
+                                               e0 + 8 + q < re ? (d2 - bi) * STRIDE : dummy,
+                                               e0 + 12 + q < re ? (d3 - bi) * STRIDE : dummy, dw0, dw1, dw2, dw3,
+                                               cbyte, acc);
+                    }
+                    acc.x += v == msrc[0] ? alpha : 0.f;
+                    acc.y += v == msrc[1] ? alpha : 0.f;
+                    acc.z += v == msrc[2] ? alpha : 0.f;
+                    acc.w += v == msrc[3] ? alpha : 0.f;
+                    xr[k] = acc;
                 }
             }
         }
         __syncthreads();
         const int r1 = opaque(row0);
+        const int n1 = opaque_s32(t.n);
 #pragma unroll
         for (int k = 0; k < kResMaxK; ++k) {
-            if (k * RPP < n) {
+            if (k * RPP < n1) {
                 const int v = r1 + k * RPP;
-                if (v < n) lds[v * COLS + c] = xr[k] * L.scale[v];
+                if (v < n1) {
+                    const float sc = L.scale[v];
+                    *reinterpret_cast<float4*>(reinterpret_cast<char*>(lds) + v * STRIDE + cbyte) =
+                        make_float4(xr[k].x * sc, xr[k].y * sc, xr[k].z * sc, xr[k].w * sc);
+                }
             }
         }
         __syncthreads();
     }
 
-    // Epilogue.  FP64 residual 1 - sum_v pi_hat(s, v): per-wave partials go
-    // to the (no longer needed) iterate area, then the unscaled iterate is
-    // written column-swizzled so that the transposed read below is
+    // Epilogue.  FP64 residual 1 - sum_v pi_hat(s, v): per-column partial sums
+    // go through the (no longer needed) iterate area; then the unscaled
+    // iterate is written column-swizzled so that the transposed read below is
     // conflict-free.
-    double part = 0.0;
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < kResMaxK; ++k) {
         const int v = row0 + k * RPP;
-        if (k * RPP < n && v < n) part += (double)xr[k];
+        if (k * RPP < n && v < n) {
+            part[0] += (double)xr[k].x;
+            part[1] += (double)xr[k].y;
+            part[2] += (double)xr[k].z;
+            part[3] += (double)xr[k].w;
+        }
     }
+    // lanes holding the same columns: same (quad % QPR, q), other row slots
 #pragma unroll
-    for (int o = COLS; o < kWave; o <<= 1) part += __shfl_xor(part, o, kWave);
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int o = 4 * QPR; o < kWave; o <<= 1) part[i] += __shfl_xor(part[i], o, kWave);
+    }
     double* red = reinterpret_cast<double*>(lds);
     __syncthreads();
-    if (rsub == 0) red[wave * kWave + c] = part;
+    if (rsub == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[wave * COLS + col0 + i] = part[i];
+    }
     __syncthreads();
     if (tid < t.ncols && a.resid) {
         double s = 0.0;
-        for (int w = 0; w < kResWaves; ++w) s += red[w * kWave + tid];
-        a.resid[t.s0 + tid] = 1.0 - s;
+        for (int w = 0; w < kResWaves; ++w) s += red[w * COLS + tid];
+        as_global_w(a.resid)[t.s0 + tid] = 1.0 - s;
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kResMaxK; ++k) {
         const int v = row0 + k * RPP;
-        if (k * RPP < n && v < n) lds[v * COLS + (c ^ (v & (COLS - 1)))] = xr[k];
+        if (k * RPP < n && v < n) {
+            const int sw = v & (COLS - 1);
+            lds[v * COLS + ((col0 + 0) ^ sw)] = xr[k].x;
+            lds[v * COLS + ((col0 + 1) ^ sw)] = xr[k].y;
+            lds[v * COLS + ((col0 + 2) ^ sw)] = xr[k].z;
+            lds[v * COLS + ((col0 + 3) ^ sw)] = xr[k].w;
+        }
     }
     __syncthreads();
     if (a.ppr_out || a.dppr_out) {
         for (int ci = 0; ci < t.ncols; ++ci) {
-            const int s_local = a.src ? a.src[t.s0 + ci] : t.s0 + ci;
-            const float dsc = a.deg[base + s_local];
+            const int s_local = a.src ? srcp[t.s0 + ci] : t.s0 + ci;
+            const float dsc = as_global(a.deg)[base + s_local];
             const int64_t row = t.out_off + (int64_t)(t.s0 + ci) * t.ld;
             for (int j = tid; j < t.n_tgt; j += kResThreads) {
-                const int tn = a.tgt ? a.tgt[j] : j;
+                const int tn = a.tgt ? as_global(a.tgt)[j] : j;
                 const float x = lds[tn * COLS + (ci ^ (tn & (COLS - 1)))];
-                if (a.ppr_out) a.ppr_out[row + j] = x;
-                if (a.dppr_out) a.dppr_out[row + j] = x * dsc;
+                if (a.ppr_out) as_global_w(a.ppr_out)[row + j] = x;
+                if (a.dppr_out) as_global_w(a.dppr_out)[row + j] = x * dsc;
             }
         }
     }
