@@ -218,6 +218,7 @@ typedef struct {
     int64_t n_nodes;         /* total node count */
     int64_t nnz;             /* total arc count, < 2^31 */
     int32_t max_n;           /* largest subgraph (host-known) */
+    int64_t pool_size;       /* sum of n_g^2 = mat_off[n_graphs] (host-known) */
     const int64_t* node_off; /* device int64[n_graphs+1]; graph g owns nodes [node_off[g], node_off[g+1]) */
     const int32_t* row_ptr;  /* device int32[n_nodes+1], global CSR over the union */
     const int32_t* col_idx;  /* device int32[nnz], global node ids (arcs never leave their subgraph) */
@@ -236,7 +237,7 @@ size_t pprviz_batch_workspace(const ppr_batch* b);
  *   delta_pool[mat_off[g] + i*n_g + j] = PDist with n_clamp = n_g
  *   x_out[2*node] = layout after stress_iters Jacobi sweeps from x0
  *   stress_out[g] = L(x_out_g | Delta_g) (DEVICE double[n_graphs], or NULL)
- * dppr_pool, delta_pool: device float[mat_off[n_graphs]].  x0, x_out: device
+ * dppr_pool, delta_pool: device float[pool_size].  x0, x_out: device
  * float[2*n_nodes], must not alias.  Every subgraph must have n_g in
  * [1, pprviz_batch_max_n()] (else PPR_EUNSUPPORTED).  Enqueues kernels on
  * `stream` without any host synchronization.

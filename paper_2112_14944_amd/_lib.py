@@ -31,7 +31,7 @@ class ppr_csr(C.Structure):
 
 
 class ppr_batch(C.Structure):
-    _fields_ = [("n_graphs", i32), ("n_nodes", i64), ("nnz", i64), ("max_n", i32), ("node_off", vp),
+    _fields_ = [("n_graphs", i32), ("n_nodes", i64), ("nnz", i64), ("max_n", i32), ("pool_size", i64), ("node_off", vp),
                 ("row_ptr", vp), ("col_idx", vp), ("mat_off", vp)]
 
 

@@ -31,6 +31,8 @@ struct BatchPlan {
     int64_t* tile_pre;   // [G+1] prefix of PPR tiles in LPT order
     int64_t* pd_pre;     // [G+1] prefix of 64x64 PDist tiles (subgraph order)
     int64_t* rb_pre;     // [G+1] prefix of 16-row layout blocks (subgraph order)
+    int32_t* pd_graph;   // subgraph of each PDist tile item
+    int32_t* rb_graph;   // subgraph of each layout row-block item
     int32_t* counter;    // [3] PPR task queue heads, one per tile width
     int32_t* cls_pos;    // [4] first LPT position of the 16-, 32- and 64-column classes, then G
 };
@@ -115,6 +117,11 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t*
         if (tid == kPlanThreads - 1) out[G] = run;
         __syncthreads();
     }
+    // item -> subgraph maps (one load per item instead of a binary search)
+    for (int g = tid; g < G; g += kPlanThreads) {
+        for (int64_t i = p.pd_pre[g]; i < p.pd_pre[g + 1]; ++i) p.pd_graph[i] = g;
+        for (int64_t i = p.rb_pre[g]; i < p.rb_pre[g + 1]; ++i) p.rb_graph[i] = g;
+    }
     // Sizes are sorted descending, so each tile width owns a contiguous range
     // of positions: n > Res<32>::NMAX (16 columns), then n > Res<64>::NMAX
     // (32 columns), then the rest (64 columns).
@@ -176,22 +183,28 @@ __global__ __launch_bounds__(kResThreads) void batch_ppr_kernel(BatchArgs b, Bat
     }
 }
 
+// PDist of every subgraph, 64x64 tiles; also writes 1/Delta (zero diagonal)
+// for the layout sweeps, with the same reciprocal the single-layout kernel
+// evaluates per pair.
 __global__ __launch_bounds__(256) void batch_pdist_kernel(const int64_t* __restrict__ node_off,
                                                           const int64_t* __restrict__ mat_off, int32_t G,
                                                           const int64_t* __restrict__ pd_pre,
-                                                          const float* __restrict__ pid, float* __restrict__ delta) {
+                                                          const int32_t* __restrict__ pd_graph,
+                                                          const float* __restrict__ pid, float* __restrict__ delta,
+                                                          float* __restrict__ inv) {
     __shared__ float tt[64][65];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int64_t total = pd_pre[G];
     for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-        const int g = find_segment(pd_pre, G, item);
+        const int g = pd_graph[item];
         const int k = graph_n(node_off, g);
         const int nt = (k + 63) / 64;
         const int64_t local = item - pd_pre[g];
         const int64_t i0 = (local / nt) * 64, j0 = (local % nt) * 64;
         const float* P = pid + mat_off[g];
         float* D = delta + mat_off[g];
+        float* V = inv + mat_off[g];
         const float hi = pdist_hi(k);
         __syncthreads();
         for (int jj = w; jj < 64; jj += 4) {
@@ -203,29 +216,34 @@ __global__ __launch_bounds__(256) void batch_pdist_kernel(const int64_t* __restr
             const int64_t i = i0 + ii, j = j0 + lane;
             if (i >= k || j >= k) continue;
             const float z = P[i * k + j] + tt[lane][ii];
-            D[i * k + j] = (i == j) ? 0.f : pdist_value(z, hi);
+            const float dv = (i == j) ? 0.f : pdist_value(z, hi);
+            D[i * k + j] = dv;
+            V[i * k + j] = (i == j) ? 0.f : __builtin_amdgcn_rcpf(dv);
         }
     }
 }
 
+// Layout row blocks of every subgraph, grid-stride over (subgraph, 16 rows).
 template <int MODE>
 __global__ __launch_bounds__(256) void batch_layout_kernel(const int64_t* __restrict__ node_off,
                                                            const int64_t* __restrict__ mat_off, int32_t G,
                                                            const int64_t* __restrict__ rb_pre,
-                                                           const float* __restrict__ delta,
+                                                           const int32_t* __restrict__ rb_graph,
+                                                           const float* __restrict__ inv,
                                                            const float2* __restrict__ x, float2* __restrict__ xout,
-                                                           double* __restrict__ part) {
+                                                           float* __restrict__ wsum, double* __restrict__ part) {
     __shared__ double red[4];
     const int wave = threadIdx.x >> 6;
     const int64_t total = rb_pre[G];
     for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-        const int g = find_segment(rb_pre, G, item);
+        const int g = rb_graph[item];
         const int k = graph_n(node_off, g);
         const int64_t rb = item - rb_pre[g];
         const int64_t nb = node_off[g];
         const int row_begin = (int)(rb * kLayoutRowsPerBlock) + wave * kLayoutRowsPerWave;
-        const double st = layout_rows<MODE>(delta + mat_off[g], k, k, x + nb, row_begin,
-                                            xout ? xout + nb : nullptr, 1.f, nullptr, nullptr);
+        const double st = layout_rows<MODE, true>(inv + mat_off[g], k, k, x + nb, row_begin,
+                                                  xout ? xout + nb : nullptr, 1.f, nullptr, nullptr,
+                                                  wsum ? wsum + nb : nullptr);
         if (MODE == kLayoutStress) {
             if ((threadIdx.x & 63) == 0) red[wave] = st;
             __syncthreads();
@@ -254,6 +272,8 @@ __global__ void copy_kernel(const float* __restrict__ a, float* __restrict__ b, 
 struct BatchWs {
     float* deg;
     float* invd;
+    float* inv;   // 1/Delta pool (zero diagonal)
+    float* wsum;  // per node sum_j Delta^-2
     float* xtmp;
     double* part;
     BatchPlan plan;
@@ -264,6 +284,8 @@ static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     BatchWs t;
     t.deg = c.template take<float>((size_t)b->n_nodes);
     t.invd = c.template take<float>((size_t)b->n_nodes);
+    t.inv = c.template take<float>((size_t)std::max<int64_t>(b->pool_size, 1));
+    t.wsum = c.template take<float>((size_t)b->n_nodes);
     t.xtmp = c.template take<float>((size_t)b->n_nodes * 2);
     // row blocks: sum over g of ceil(n_g/16) <= n_nodes/16 + G
     t.part = c.template take<double>((size_t)(b->n_nodes / kLayoutRowsPerBlock + b->n_graphs + 1));
@@ -271,6 +293,10 @@ static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     t.plan.tile_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
     t.plan.pd_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
     t.plan.rb_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
+    // item counts: sum_g ceil(n_g/64)^2 <= pool/4096 + n_nodes/32 + G, and
+    // sum_g ceil(n_g/16) <= n_nodes/16 + G
+    t.plan.pd_graph = c.template take<int32_t>((size_t)(b->pool_size / 4096 + b->n_nodes / 32 + b->n_graphs + 1));
+    t.plan.rb_graph = c.template take<int32_t>((size_t)(b->n_nodes / kLayoutRowsPerBlock + b->n_graphs + 1));
     t.plan.counter = c.template take<int32_t>(64);
     t.plan.cls_pos = c.template take<int32_t>(64);
     if (w) *w = t;
@@ -290,7 +316,7 @@ static ppr_status batch_validate(const ppr_batch* b, float alpha, int32_t max_it
     if (!b->node_off || !b->row_ptr || (b->nnz > 0 && !b->col_idx) || !b->mat_off) return PPR_EINVAL;
     if (!(alpha > 0.0f && alpha < 1.0f) || max_iter < 0 || stress_iters < 0) return PPR_EINVAL;
     if (!x0 || !x_out || x0 == x_out || !dppr_pool || !delta_pool) return PPR_EINVAL;
-    if (b->max_n < 1) return PPR_EINVAL;
+    if (b->max_n < 1 || b->pool_size < b->n_nodes) return PPR_EINVAL;
     if (b->max_n > kBatchMaxN) return PPR_EUNSUPPORTED;
     return PPR_OK;
 }
@@ -331,7 +357,10 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
 
     const unsigned grid = (unsigned)cus * 16;
     hipLaunchKernelGGL(batch_pdist_kernel, dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off, G, w.plan.pd_pre,
-                       dppr_pool, delta_pool);
+                       w.plan.pd_graph, dppr_pool, delta_pool, w.inv);
+    hipLaunchKernelGGL((batch_layout_kernel<kLayoutWsum>), dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off, G,
+                       w.plan.rb_pre, w.plan.rb_graph, w.inv, reinterpret_cast<const float2*>(x0), nullptr, w.wsum,
+                       nullptr);
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[3], s));
 
     // Jacobi sweeps, ping-pong so that the last one lands in x_out.
@@ -345,13 +374,13 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     for (int it = 0; it < stress_iters; ++it) {
         float2* out = bufs[next];
         hipLaunchKernelGGL((batch_layout_kernel<kLayoutStep>), dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off, G,
-                           w.plan.rb_pre, delta_pool, cur, out, nullptr);
+                           w.plan.rb_pre, w.plan.rb_graph, w.inv, cur, out, w.wsum, nullptr);
         cur = out;
         next ^= 1;
     }
     if (stress_out) {
         hipLaunchKernelGGL((batch_layout_kernel<kLayoutStress>), dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off,
-                           G, w.plan.rb_pre, delta_pool, cur, nullptr, w.part);
+                           G, w.plan.rb_pre, w.plan.rb_graph, w.inv, cur, nullptr, nullptr, w.part);
         hipLaunchKernelGGL(batch_stress_sum_kernel, dim3((G + 255) / 256), dim3(256), 0, s, w.plan.rb_pre, G, w.part,
                            stress_out);
     }

@@ -31,83 +31,139 @@ enum {
     kLayoutStress = 2,      // stress partials only
     kLayoutGradX = 3,       // dL/dX
     kLayoutGradBoth = 4,    // dL/dX (optional) and dL/dDelta
+    kLayoutWsum = 5,        // per-row sum_j Delta_ij^-2 (the diagonal of L^w)
 };
+
+// Squared distances are floored here before the reciprocal square root, so
+// that a coincident pair (and the diagonal) gets a finite 1/d; its direction
+// term c * (X_i - X_j) is then exactly zero because X_i - X_j is.
+constexpr float kMinSq = 1e-30f;
 
 constexpr int kLayoutRowsPerWave = 4;
 constexpr int kLayoutRowsPerBlock = 4 * kLayoutRowsPerWave;
+
+// Work of one pair (i, j), accumulated into the row's running sums (see
+// layout_rows for the formulas).
+template <int MODE, bool INV>
+__device__ __forceinline__ void layout_pair(float Dv, bool off, float2 xi, float2 xj, float& ax, float& ay,
+                                            float& aw, float& as, bool acc_w, float scale, float* gd_ij) {
+    constexpr bool STEP = (MODE == kLayoutStep || MODE == kLayoutStepStress);
+    constexpr bool STRESS = (MODE == kLayoutStepStress || MODE == kLayoutStress);
+    constexpr bool GRAD = (MODE == kLayoutGradX || MODE == kLayoutGradBoth);
+    constexpr bool WSUM = (MODE == kLayoutWsum);
+    const float inv = INV ? Dv : (off ? __builtin_amdgcn_rcpf(Dv) : 0.f);
+    const float w = inv * inv;
+    if (acc_w) aw += w;
+    if (WSUM) return;
+    const float dx = xi.x - xj.x;
+    const float dy = xi.y - xj.y;
+    const float r2 = fmaf(dx, dx, dy * dy);
+    const float rs = __builtin_amdgcn_rsqf(fmaxf(r2, kMinSq));
+    if (STEP) {
+        const float c = inv * rs;
+        ax = fmaf(w, xj.x, fmaf(c, dx, ax));
+        ay = fmaf(w, xj.y, fmaf(c, dy, ay));
+    }
+    if (STRESS || GRAD) {
+        const float d = r2 * rs;
+        const float t = fmaf(-d, inv, 1.0f);
+        if (STRESS) as = off ? fmaf(t, t, as) : as;
+        if (GRAD) {
+            const float g = 2.0f * (d - Dv) * w * rs;
+            ax = fmaf(g, dx, ax);
+            ay = fmaf(g, dy, ay);
+            if (MODE == kLayoutGradBoth) *gd_ij = off ? scale * 2.0f * t * d * w : 0.f;
+        }
+    }
+}
 
 // Pairwise work of 4 consecutive rows i (one wave) against all j of a
 // k-node layout.  Lanes stride over j, so each row of Delta is read
 // coalesced and each X_j load serves 4 rows.
 //   step:   X+_i = (sum_j w X_j + c (X_i - X_j)) / sum_j w,
 //           w = Delta^-2, c = w Delta / d = Delta^-1 d^-1  (Jacobi sweep of
-//           L^w X = L^Y Y; a coincident pair has d = 0 and adds only w X_j)
+//           L^w X = L^Y Y; a coincident pair adds only w X_j)
 //   stress: sum_{j != i} (1 - d/Delta)^2, halved per unordered pair
 //   grad:   dL/dX_i = sum_j 2 w (d - Delta) (X_i - X_j)/d,
 //           dL/dDelta_ij = 2 (1 - d/Delta) d / Delta^2
+// INV: `delta` holds 1/Delta with a zero diagonal (precomputed once for many
+// sweeps) instead of Delta.  wsum: per-row sum_j w precomputed by the
+// kLayoutWsum pass (same summation order), or nullptr to accumulate it here.
+// Full groups of 4 rows take a branch-free path that issues the loads of 4
+// columns (16 Delta values, 4 positions) before their arithmetic.
 // Returns this wave's stress contribution (lane 0 holds the wave total).
-template <int MODE>
+template <int MODE, bool INV>
 __device__ __forceinline__ double layout_rows(const float* __restrict__ delta, int64_t ld, int32_t k,
                                               const float2* __restrict__ x, int row_begin,
                                               float2* __restrict__ xout, float scale,
-                                              float2* __restrict__ gx, float* __restrict__ gd) {
+                                              float2* __restrict__ gx, float* __restrict__ gd,
+                                              float* __restrict__ wsum) {
+    constexpr int R = kLayoutRowsPerWave;
     constexpr bool STEP = (MODE == kLayoutStep || MODE == kLayoutStepStress);
     constexpr bool STRESS = (MODE == kLayoutStepStress || MODE == kLayoutStress);
     constexpr bool GRAD = (MODE == kLayoutGradX || MODE == kLayoutGradBoth);
+    constexpr bool WSUM = (MODE == kLayoutWsum);
+    static_assert(!(INV && GRAD), "the gradient needs Delta itself");
     const int lane = threadIdx.x & 63;
-    float2 xi[kLayoutRowsPerWave];
-    bool ok[kLayoutRowsPerWave];
-    float ax[kLayoutRowsPerWave], ay[kLayoutRowsPerWave], aw[kLayoutRowsPerWave], as[kLayoutRowsPerWave];
+    const bool acc_w = WSUM || (STEP && wsum == nullptr);
+    float2 xi[R];
+    bool ok[R];
+    float ax[R], ay[R], aw[R], as[R];
 #pragma unroll
-    for (int r = 0; r < kLayoutRowsPerWave; ++r) {
+    for (int r = 0; r < R; ++r) {
         const int i = row_begin + r;
         ok[r] = i < k;
         xi[r] = ok[r] ? x[i] : make_float2(0.f, 0.f);
         ax[r] = ay[r] = aw[r] = as[r] = 0.f;
     }
-    for (int j = lane; j < k; j += kWave) {
-        const float2 xj = x[j];
+    int j = lane;
+    if (row_begin + R <= k) {
+        const float* __restrict__ drow = delta + (int64_t)row_begin * ld;
+        for (; j + 3 * kWave < k; j += 4 * kWave) {
+            float2 xv[4];
+            float dv[4][R];
 #pragma unroll
-        for (int r = 0; r < kLayoutRowsPerWave; ++r) {
-            if (!ok[r]) continue;
-            const int i = row_begin + r;
-            const float D = delta[(int64_t)i * ld + j];
-            const bool off = (j != i);
-            const float dx = xi[r].x - xj.x;
-            const float dy = xi[r].y - xj.y;
-            const float r2 = fmaf(dx, dx, dy * dy);
-            const float rs = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
-            const float inv = off ? __builtin_amdgcn_rcpf(D) : 0.f;
-            const float w = inv * inv;
-            if (STEP) {
-                const float c = inv * rs;
-                ax[r] = fmaf(w, xj.x, fmaf(c, dx, ax[r]));
-                ay[r] = fmaf(w, xj.y, fmaf(c, dy, ay[r]));
-                aw[r] += w;
+            for (int u = 0; u < 4; ++u) {
+                xv[u] = x[j + u * kWave];
+#pragma unroll
+                for (int r = 0; r < R; ++r) dv[u][r] = drow[(int64_t)r * ld + j + u * kWave];
             }
-            if (STRESS || GRAD) {
-                const float d = r2 * rs;
-                const float t = fmaf(-d, inv, 1.0f);
-                if (STRESS) as[r] = off ? fmaf(t, t, as[r]) : as[r];
-                if (GRAD) {
-                    const float g = 2.0f * (d - D) * w * rs;
-                    ax[r] = fmaf(g, dx, ax[r]);
-                    ay[r] = fmaf(g, dy, ay[r]);
-                    if (MODE == kLayoutGradBoth) gd[(int64_t)i * ld + j] = off ? scale * 2.0f * t * d * w : 0.f;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int jj = j + u * kWave;
+                    layout_pair<MODE, INV>(dv[u][r], jj != row_begin + r, xi[r], xv[u], ax[r], ay[r], aw[r], as[r],
+                                           acc_w, scale,
+                                           GRAD ? gd + (int64_t)(row_begin + r) * ld + jj : nullptr);
                 }
             }
         }
     }
+    for (; j < k; j += kWave) {
+        const float2 xj = x[j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!ok[r]) continue;
+            const int i = row_begin + r;
+            layout_pair<MODE, INV>(delta[(int64_t)i * ld + j], j != i, xi[r], xj, ax[r], ay[r], aw[r], as[r], acc_w,
+                                   scale, GRAD ? gd + (int64_t)i * ld + j : nullptr);
+        }
+    }
     double st = 0.0;
 #pragma unroll
-    for (int r = 0; r < kLayoutRowsPerWave; ++r) {
+    for (int r = 0; r < R; ++r) {
         if (!ok[r]) continue;  // wave-uniform
         const int i = row_begin + r;
+        if (WSUM) {
+            const float sw = wave_sum(aw[r]);
+            if (lane == 0) wsum[i] = sw;
+        }
         if (STEP || GRAD) {
             const float sx = wave_sum(ax[r]);
             const float sy = wave_sum(ay[r]);
             if (STEP) {
-                const float sw = wave_sum(aw[r]);
+                const float sw = wsum ? wsum[i] : wave_sum(aw[r]);
                 if (lane == 0) xout[i] = sw > 0.f ? make_float2(sx / sw, sy / sw) : xi[r];
             } else if (gx && lane == 0) {
                 gx[i] = make_float2(scale * sx, scale * sy);
@@ -127,7 +183,7 @@ __global__ __launch_bounds__(256) void layout_rows_kernel(const float* __restric
     __shared__ double red[4];
     const int wave = threadIdx.x >> 6;
     const int row_begin = blockIdx.x * kLayoutRowsPerBlock + wave * kLayoutRowsPerWave;
-    const double st = layout_rows<MODE>(delta, ld, k, x, row_begin, xout, scale, gx, gd);
+    const double st = layout_rows<MODE, false>(delta, ld, k, x, row_begin, xout, scale, gx, gd, nullptr);
     if (MODE == kLayoutStepStress || MODE == kLayoutStress) {
         if ((threadIdx.x & 63) == 0) red[wave] = st;
         __syncthreads();

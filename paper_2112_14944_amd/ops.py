@@ -194,7 +194,7 @@ class Batch:
         self.pool = int(gb.mat_off[-1])
 
     def c(self):
-        return L.ppr_batch(self.n_graphs, self.n_nodes, self.nnz, self.max_n, _ptr(self.node_off),
+        return L.ppr_batch(self.n_graphs, self.n_nodes, self.nnz, self.max_n, self.pool, _ptr(self.node_off),
                            _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.mat_off))
 
     def buffers(self, x0):

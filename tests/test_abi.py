@@ -92,12 +92,12 @@ def test_argument_validation_before_any_gpu_work(lib):
 def test_batch_validation_and_limits(lib):
     assert lib.pprviz_batch_max_n() == 2304
     p = C.c_void_p(64)
-    big = L.ppr_batch(2, 5000, 10, 2305, p, p, p, p)
+    big = L.ppr_batch(2, 5000, 10, 2305, 5000 * 2305, p, p, p, p)
     ws_big = lib.pprviz_batch_workspace(C.byref(big))
     assert ws_big > 0
     assert lib.pprviz_batch(C.byref(big), 0.15, 1e-6, 100, 10, p, C.c_void_p(128), p, p, None, p, ws_big,
                             None) == L.PPR_EUNSUPPORTED
-    ok = L.ppr_batch(2, 5000, 10, 100, p, p, p, p)
+    ok = L.ppr_batch(2, 5000, 10, 100, 5000 * 100, p, p, p, p)
     assert lib.pprviz_batch(C.byref(ok), 0.15, 1e-6, 100, 10, p, p, p, p, None, p, 1 << 30,
                             None) == L.PPR_EINVAL  # x0 aliases x_out
     assert lib.pprviz_batch(C.byref(ok), 0.15, 1e-6, 100, 10, p, C.c_void_p(128), p, p, None, p, 16,
