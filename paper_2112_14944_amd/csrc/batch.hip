@@ -270,6 +270,7 @@ __global__ void copy_kernel(const float* __restrict__ a, float* __restrict__ b, 
 }
 
 struct BatchWs {
+    RowEnt* rows;
     float* deg;
     float* invd;
     float* inv;   // 1/Delta pool (zero diagonal)
@@ -282,6 +283,7 @@ struct BatchWs {
 template <typename Cursor>
 static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     BatchWs t;
+    t.rows = c.template take<RowEnt>((size_t)b->n_nodes);
     t.deg = c.template take<float>((size_t)b->n_nodes);
     t.invd = c.template take<float>((size_t)b->n_nodes);
     t.inv = c.template take<float>((size_t)std::max<int64_t>(b->pool_size, 1));
@@ -330,6 +332,7 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     const int G = b->n_graphs;
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[0], s));
     launch_degree(b->row_ptr, nullptr, b->n_nodes, w.deg, w.invd, s);
+    launch_row_table(b->row_ptr, b->node_off, 0, G, w.rows, s);
     hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, b->node_off, G, w.plan);
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[1], s));
 
@@ -337,6 +340,7 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     ba.node_off = b->node_off;
     ba.mat_off = b->mat_off;
     ba.G = G;
+    ba.r.rows = w.rows;
     ba.r.row_ptr = b->row_ptr;
     ba.r.col_idx = b->col_idx;
     ba.r.weight = nullptr;

@@ -92,6 +92,7 @@ __global__ void edge_sum_kernel(const int32_t* __restrict__ row_ptr, const int32
 }
 
 struct BwdWs {
+    RowEnt* rows;
     float* deg;
     float* invd;
     float* ya;
@@ -108,6 +109,7 @@ template <typename Cursor>
 static void bwd_layout(Cursor& c, int n, int64_t nnz, bool recompute, BwdWs* w) {
     const int64_t ld = stream_ld(n);
     BwdWs t;
+    t.rows = c.template take<RowEnt>(n);
     t.deg = c.template take<float>(n);
     t.invd = c.template take<float>(n);
     t.ya = c.template take<float>((size_t)n * ld);
@@ -154,8 +156,8 @@ ppr_status ppr_matrix_backward(const ppr_csr* g, float alpha, int32_t T, const f
     launch_degree(g->row_ptr, g->weight, n, w.deg, w.invd, s);
     const float* pi = ppr;
     if (recompute) {
-        ppr_forward(g, nullptr, n, nullptr, n, alpha, T, w.pi, nullptr, w.deg, w.invd, nullptr, w.ya, w.yb, w.part,
-                    s);
+        ppr_forward(g, nullptr, n, nullptr, n, alpha, T, w.pi, nullptr, w.deg, w.invd, nullptr, w.rows, w.ya, w.yb,
+                    w.part, s);
         pi = w.pi;
     }
     StreamArgs sa;

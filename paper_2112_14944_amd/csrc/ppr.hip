@@ -27,6 +27,54 @@ __global__ void degree_kernel(const int32_t* __restrict__ row_ptr, const float* 
     invd[v] = (re > rs && d > 0.f) ? 1.0f / d : 1.0f;
 }
 
+__global__ __launch_bounds__(256) void row_table_kernel(const int32_t* __restrict__ row_ptr,
+                                                       const int64_t* __restrict__ node_off, int32_t n_single,
+                                                       RowEnt* __restrict__ table) {
+    constexpr int kMaxRows = 4096;
+    __shared__ uint32_t key[kMaxRows];
+    const int g = blockIdx.x;
+    const int64_t base = node_off ? node_off[g] : 0;
+    const int n = node_off ? (int)(node_off[g + 1] - base) : n_single;
+    if (n <= 0 || n > kMaxRows) return;  // larger graphs never use the resident tile
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += 256) {
+        if (i < n) {
+            const int d = min(row_ptr[base + i + 1] - row_ptr[base + i], 4095);
+            key[i] = ((uint32_t)(4095 - d) << 12) | (uint32_t)i;
+        } else {
+            key[i] = 0xFFFFFFFFu;
+        }
+    }
+    __syncthreads();
+    // bitonic sort, ascending key = descending degree, ties by row id
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += 256) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const uint32_t x = key[i], y = key[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        key[i] = y;
+                        key[ixj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const int v = (int)(key[i] & 4095u);
+        table[base + i] = RowEnt{row_ptr[base + v], row_ptr[base + v + 1], v, 0};
+    }
+}
+
+void launch_row_table(const int32_t* row_ptr, const int64_t* node_off, int32_t n_single, int32_t blocks,
+                      RowEnt* table, hipStream_t s) {
+    hipLaunchKernelGGL(row_table_kernel, dim3(blocks), dim3(256), 0, s, row_ptr, node_off, n_single, table);
+}
+
 template <int COLS, bool WEIGHTED>
 __global__ __launch_bounds__(kResThreads) void ppr_resident_kernel(ResArgs a, int32_t n, int32_t n_src,
                                                                  int32_t n_tgt) {
@@ -59,6 +107,7 @@ static void launch_resident(bool weighted, const ResArgs& a, int n, int n_src, i
 
 // Workspace layout of ppr_matrix.
 struct PprWs {
+    RowEnt* rows;
     float* deg;
     float* invd;
     double* resid;
@@ -80,10 +129,12 @@ bool use_resident(int n) { return res_cols_for(n) != 0; }
 // the LDS-resident kernel.
 void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int32_t* tgt, int32_t n_tgt,
                  float alpha, int32_t T, float* ppr_out, float* dppr_out, const float* deg, const float* invd,
-                 double* resid, float* ya, float* yb, double* part, hipStream_t s) {
+                 double* resid, RowEnt* rows, float* ya, float* yb, double* part, hipStream_t s) {
     const int n = g->n;
     if (use_resident(n)) {
+        launch_row_table(g->row_ptr, nullptr, n, 1, rows, s);
         ResArgs a;
+        a.rows = rows;
         a.row_ptr = g->row_ptr;
         a.col_idx = g->col_idx;
         a.weight = g->weight;
@@ -124,10 +175,12 @@ void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int3
 
 template <typename Cursor>
 static void ppr_ws_layout(Cursor& c, int n, int n_src, PprWs* w) {
+    auto* rows = c.template take<RowEnt>(n);
     auto* deg = c.template take<float>(n);
     auto* invd = c.template take<float>(n);
     auto* resid = c.template take<double>(std::max(n_src, 1));
     if (w) {
+        w->rows = rows;
         w->deg = deg;
         w->invd = invd;
         w->resid = resid;
@@ -230,8 +283,8 @@ ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src, const
     const int n = g->n;
     launch_degree(g->row_ptr, g->weight, n, w.deg, w.invd, s);
 
-    ppr_forward(g, src, n_src, tgt, n_tgt, alpha, T, ppr_out, dppr_out, w.deg, w.invd, w.resid, w.ya, w.yb, w.part,
-                s);
+    ppr_forward(g, src, n_src, tgt, n_tgt, alpha, T, ppr_out, dppr_out, w.deg, w.invd, w.resid, w.rows, w.ya, w.yb,
+                w.part, s);
     st = launch_status();
     if (st != PPR_OK) return st;
     if (resid_out) {

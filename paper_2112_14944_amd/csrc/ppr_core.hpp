@@ -58,7 +58,25 @@ struct TileTask {
     int64_t ld;       // output leading dimension
 };
 
+// Row table entry: a row of the resident tile's slot order.
+struct __attribute__((aligned(16))) RowEnt {
+    int32_t rs;   // first arc
+    int32_t re;   // one past the last arc
+    int32_t v;    // row id (local to its graph)
+    int32_t pad;
+};
+
+__device__ __forceinline__ RowEnt load_row(gcptr<RowEnt> p, int64_t i) {
+    RowEnt e;
+    e.rs = p[i].rs;
+    e.re = p[i].re;
+    e.v = p[i].v;
+    e.pad = 0;
+    return e;
+}
+
 struct ResArgs {
+    const RowEnt* rows;      // per graph, rows in slot order (row_table_kernel)
     const int32_t* row_ptr;  // global CSR row pointers
     const int32_t* col_idx;  // global node ids
     const float* weight;     // arc weights, or nullptr
@@ -87,10 +105,11 @@ __device__ __forceinline__ float4 lds_load4(const float* lds, int byte_off) {
     return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(lds) + byte_off);
 }
 
-// One chunk of 16 arcs of a quad's row: arc m sits in lane m%4, word m/4
-// (a0..a3 hold LDS byte offsets of the neighbours' rows, a zero row past the
-// row's end).  Eight 16-byte reads are issued before their adds.
-template <bool WEIGHTED>
+// One chunk of 16 arcs (NW = 4 words) or 8 arcs (NW = 2) of a quad's row: arc
+// m sits in lane m%4, word m/4 (a0..a3 hold LDS byte offsets of the
+// neighbours' rows, a zero row past the row's end).  Eight 16-byte reads are
+// issued before their adds.
+template <bool WEIGHTED, int NW>
 __device__ __forceinline__ void gather_chunk(const float* __restrict__ lds, int a0, int a1, int a2, int a3,
                                              float w0, float w1, float w2, float w3, int cbyte, float4& acc) {
 #define PPRVIZ_RD(M, A) y[(M) & 7] = lds_load4(lds, quad_bcast<(M) % 4>(A) + cbyte);
@@ -113,6 +132,7 @@ __device__ __forceinline__ void gather_chunk(const float* __restrict__ lds, int 
     __builtin_amdgcn_sched_barrier(0);
     PPRVIZ_ACC(0, w0) PPRVIZ_ACC(1, w0) PPRVIZ_ACC(2, w0) PPRVIZ_ACC(3, w0)
     PPRVIZ_ACC(4, w1) PPRVIZ_ACC(5, w1) PPRVIZ_ACC(6, w1) PPRVIZ_ACC(7, w1)
+    if (NW == 2) return;
     __builtin_amdgcn_sched_barrier(0);
     PPRVIZ_RD(8, a2) PPRVIZ_RD(9, a2) PPRVIZ_RD(10, a2) PPRVIZ_RD(11, a2)
     PPRVIZ_RD(12, a3) PPRVIZ_RD(13, a3) PPRVIZ_RD(14, a3) PPRVIZ_RD(15, a3)
@@ -211,71 +231,73 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
     __syncthreads();
 
     float4 xr[kResMaxK];
-    const int row0 = wave * RPW + rsub;  // row of pass k is row0 + k * RPP
+    int vs[kResMaxK];  // row id of each slot
+    const int row0 = wave * RPW + rsub;  // slot of pass k is row0 + k * RPP
 #pragma unroll
     for (int k = 0; k < kResMaxK; ++k) {
-        const int v = row0 + k * RPP;
+        const int slot = row0 + k * RPP;
+        const int v = slot < n ? as_global(a.rows)[base + slot].v : -1;
+        vs[k] = v;
         const bool on = a.T >= 1;
         xr[k] = make_float4(on && v == msrc[0] ? alpha : 0.f, on && v == msrc[1] ? alpha : 0.f,
                             on && v == msrc[2] ? alpha : 0.f, on && v == msrc[3] ? alpha : 0.f);
     }
 
+    const gcptr<RowEnt> rows = as_global(a.rows);
     for (int it = 1; it < a.T; ++it) {
         const int r0 = opaque(row0);
         const int64_t b = opaque_s(base);
         const int bi = (int)b;
         const int n = opaque_s32(t.n);
         const int dummy = n * STRIDE;
-        // Row-level software pipeline: the first chunk of row k+1 and the
-        // bounds of row k+2 are loaded while row k is summed.
-        int rs1 = 0, re1 = 0, rs2 = 0, re2 = 0;
-        if (r0 < n) {
-            rs1 = rp[b + r0];
-            re1 = rp[b + r0 + 1];
-        }
-        if (r0 + RPP < n) {
-            rs2 = rp[b + r0 + RPP];
-            re2 = rp[b + r0 + RPP + 1];
-        }
+        // Rows are visited in slot order (degree-sorted, so the rows that
+        // share a pass have similar length).  Row-level software pipeline:
+        // the first chunk of slot k+1 and the table entry of slot k+2 are
+        // loaded while slot k is summed.
+        RowEnt e1 = {0, 0, 0, 0}, e2 = {0, 0, 0, 0};
+        if (r0 < n) e1 = load_row(rows, b + r0);
+        if (r0 + RPP < n) e2 = load_row(rows, b + r0 + RPP);
         int p0 = 0, p1 = 0, p2 = 0, p3 = 0;
         float pw0 = 0.f, pw1 = 0.f, pw2 = 0.f, pw3 = 0.f;
-        load_chunk<WEIGHTED>(pc, pw, rs1, re1, q, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
+        load_chunk<WEIGHTED>(pc, pw, e1.rs, e1.re, q, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
 #pragma unroll
         for (int k = 0; k < kResMaxK; ++k) {
             if (k * RPP < n) {
-                const int v = r0 + k * RPP;
-                const int rs = rs1, re = re1;
+                const int slot = r0 + k * RPP;
+                const int rs = e1.rs, re = e1.re, v = e1.v;
                 const int c0 = p0, c1 = p1, c2 = p2, c3 = p3;
                 const float cw0 = pw0, cw1 = pw1, cw2 = pw2, cw3 = pw3;
-                rs1 = rs2;
-                re1 = re2;
-                if (k + 1 < kResMaxK && v + RPP < n)
-                    load_chunk<WEIGHTED>(pc, pw, rs1, re1, q, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
-                if (k + 2 < kResMaxK && v + 2 * RPP < n) {
-                    rs2 = rp[b + v + 2 * RPP];
-                    re2 = rp[b + v + 2 * RPP + 1];
-                }
-                if (v < n) {
+                e1 = e2;
+                if (k + 1 < kResMaxK && slot + RPP < n)
+                    load_chunk<WEIGHTED>(pc, pw, e1.rs, e1.re, q, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
+                if (k + 2 < kResMaxK && slot + 2 * RPP < n) e2 = load_row(rows, b + slot + 2 * RPP);
+                if (slot < n) {
+                    vs[k] = v;
                     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
                     if (rs == re) acc = lds_load4(lds, v * STRIDE + cbyte);
                     if (rs < re) {
-                        gather_chunk<WEIGHTED>(lds, rs + q < re ? (c0 - bi) * STRIDE : dummy,
-                                               rs + 4 + q < re ? (c1 - bi) * STRIDE : dummy,
-                                               rs + 8 + q < re ? (c2 - bi) * STRIDE : dummy,
-                                               rs + 12 + q < re ? (c3 - bi) * STRIDE : dummy, cw0, cw1, cw2, cw3,
-                                               cbyte, acc);
+                        gather_chunk<WEIGHTED, 4>(lds, rs + q < re ? (c0 - bi) * STRIDE : dummy,
+                                                  rs + 4 + q < re ? (c1 - bi) * STRIDE : dummy,
+                                                  rs + 8 + q < re ? (c2 - bi) * STRIDE : dummy,
+                                                  rs + 12 + q < re ? (c3 - bi) * STRIDE : dummy, cw0, cw1, cw2,
+                                                  cw3, cbyte, acc);
                     }
-                    // further chunks of rows longer than 16 arcs
+                    // further chunks of rows longer than 16 arcs; a tail of
+                    // at most 8 arcs takes a half chunk
 #pragma nounroll
                     for (int e0 = rs + 16; e0 < re; e0 += 16) {
                         int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
                         float dw0 = 0.f, dw1 = 0.f, dw2 = 0.f, dw3 = 0.f;
                         load_chunk<WEIGHTED>(pc, pw, e0, re, q, d0, d1, d2, d3, dw0, dw1, dw2, dw3);
-                        gather_chunk<WEIGHTED>(lds, e0 + q < re ? (d0 - bi) * STRIDE : dummy,
-                                               e0 + 4 + q < re ? (d1 - bi) * STRIDE : dummy,
-                                               e0 + 8 + q < re ? (d2 - bi) * STRIDE : dummy,
-                                               e0 + 12 + q < re ? (d3 - bi) * STRIDE : dummy, dw0, dw1, dw2, dw3,
-                                               cbyte, acc);
+                        const int a0 = e0 + q < re ? (d0 - bi) * STRIDE : dummy;
+                        const int a1 = e0 + 4 + q < re ? (d1 - bi) * STRIDE : dummy;
+                        if (re - e0 > 8) {
+                            gather_chunk<WEIGHTED, 4>(lds, a0, a1, e0 + 8 + q < re ? (d2 - bi) * STRIDE : dummy,
+                                                      e0 + 12 + q < re ? (d3 - bi) * STRIDE : dummy, dw0, dw1,
+                                                      dw2, dw3, cbyte, acc);
+                        } else {
+                            gather_chunk<WEIGHTED, 2>(lds, a0, a1, dummy, dummy, dw0, dw1, 0.f, 0.f, cbyte, acc);
+                        }
                     }
                     acc.x += v == msrc[0] ? alpha : 0.f;
                     acc.y += v == msrc[1] ? alpha : 0.f;
@@ -291,8 +313,9 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
 #pragma unroll
         for (int k = 0; k < kResMaxK; ++k) {
             if (k * RPP < n1) {
-                const int v = r1 + k * RPP;
-                if (v < n1) {
+                const int slot = r1 + k * RPP;
+                if (slot < n1) {
+                    const int v = vs[k];
                     const float sc = L.scale[v];
                     *reinterpret_cast<float4*>(reinterpret_cast<char*>(lds) + v * STRIDE + cbyte) =
                         make_float4(xr[k].x * sc, xr[k].y * sc, xr[k].z * sc, xr[k].w * sc);
@@ -309,8 +332,8 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
     double part[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < kResMaxK; ++k) {
-        const int v = row0 + k * RPP;
-        if (k * RPP < n && v < n) {
+        const int slot = row0 + k * RPP;
+        if (k * RPP < n && slot < n) {
             part[0] += (double)xr[k].x;
             part[1] += (double)xr[k].y;
             part[2] += (double)xr[k].z;
@@ -338,8 +361,9 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kResMaxK; ++k) {
-        const int v = row0 + k * RPP;
-        if (k * RPP < n && v < n) {
+        const int slot = row0 + k * RPP;
+        if (k * RPP < n && slot < n) {
+            const int v = vs[k];
             const int sw = v & (COLS - 1);
             lds[v * COLS + ((col0 + 0) ^ sw)] = xr[k].x;
             lds[v * COLS + ((col0 + 1) ^ sw)] = xr[k].y;
@@ -363,6 +387,12 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
     }
     __syncthreads();
 }
+
+// Slot order of the rows of each graph for the resident tile: rows sorted by
+// degree, longest first (ties by row id); one block per graph.  node_off ==
+// nullptr means a single graph of n_single nodes.
+__global__ void row_table_kernel(const int32_t* __restrict__ row_ptr, const int64_t* __restrict__ node_off,
+                                 int32_t n_single, RowEnt* __restrict__ table);
 
 // Degree and inverse degree of every node (the d of Definition def:pprdist is
 // the out-degree; with weights, the sum of the node's arc weights).
