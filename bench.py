@@ -100,6 +100,86 @@ def cpu_baseline(graphs, sample_count=8):
                 seconds=dt, host_cpus=len(os.sched_getaffinity(0)))
 
 
+def stage_rooflines(gb, T, ms):
+    """Roofline records of the batched stages from the library's stage times.
+
+    PPR (three persistent launches, one per tile class, timed together):
+    algorithmic bytes per push are those a streaming SpMM must move, per
+    subgraph 8 n^2 (read X_t, write X_t+1, S = n sources) + 4 nnz + 8 n + 4
+    (column indices, row pointers, 1/d); T - 1 pushes follow the initial
+    iterate.  The tile keeps X on chip, so its HBM traffic is far below this;
+    its own limit is the LDS gather, reported as FP32 adds per second.
+    Layout (one launch per sweep): 4 n^2 bytes of 1/Delta plus 20 n of
+    positions and weight sums per subgraph and sweep."""
+    sizes = gb.sizes.astype(np.float64)
+    nnz = np.diff(gb.row_ptr.astype(np.int64))
+    arcs = np.add.reduceat(nnz, gb.node_off[:-1].astype(np.int64)).astype(np.float64)
+    pushes = max(T - 1, 0)
+    ppr_bytes = pushes * float((8.0 * sizes * sizes + 4.0 * arcs + 8.0 * sizes + 4.0).sum())
+    ppr_adds = pushes * float((arcs * sizes).sum())
+    layout_bytes = float((4.0 * sizes * sizes + 20.0 * sizes).sum())
+    ppr_ms, layout_ms = ms[1], ms[3]
+    lay_launch_ms = layout_ms / (STRESS_ITERS + 1)
+    st_ppr = dict(kernel="batch_ppr_kernel", ms=ppr_ms, launches=3, bound="hbm", unit="GB/s",
+                  achieved=ppr_bytes / (ppr_ms * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
+                  work=f"{ppr_bytes:.4g} B over {pushes} pushes (X read and written once per push, plus CSR)",
+                  adds_per_s=ppr_adds / (ppr_ms * 1e-3), adds=ppr_adds)
+    st_ppr["frac"] = st_ppr["achieved"] / PEAK_HBM_GBS
+    st_lay = dict(kernel="batch_layout_kernel", ms=layout_ms, launches=STRESS_ITERS + 1, bound="hbm",
+                  unit="GB/s", achieved=layout_bytes / (lay_launch_ms * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
+                  work=f"{layout_bytes:.4g} B per sweep (1/Delta read once, X in and out, weight sums)")
+    st_lay["frac"] = st_lay["achieved"] / PEAK_HBM_GBS
+    return dict(plan_ms=ms[0], ppr=st_ppr, pdist_ms=ms[2], layout=st_lay)
+
+
+def spmm_stream(ops, dev, n=20000, gamma=2.5, avg_degree=20, tol=1e-7, reps=2):
+    """The streaming SpMM (graphs above the on-chip tile size): all-pairs PPR
+    on a Chung-Lu graph, n = 20000, exponent 2.5, mean degree 20, to L1 1e-7.
+    Algorithmic bytes per push: 8 n ld (X read and written once, ld = n
+    rounded up to 64 columns) + 4 nnz + 8 (n + 1)."""
+    import torch
+    import synth
+
+    g = synth.chung_lu(n, gamma, avg_degree, synth.BASE_SEED + 2)
+    csr = ops.Csr.from_graph(g, dev)
+    src = torch.arange(n, dtype=torch.int32, device=dev)
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, dppr, T, _ = ops.ppr_matrix(csr, src, None, alpha=ALPHA, tol=tol, want_ppr=False, want_dppr=True)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+        del dppr
+    ld = (n + 63) // 64 * 64
+    nnz = int(g.col_idx.shape[0])
+    alg = (T - 1) * (8.0 * n * ld + 4.0 * nnz + 8.0 * (n + 1))
+    return dict(workload=f"chung_lu n={n} gamma={gamma} mean degree {avg_degree}, all {n} sources, "
+                         f"L1 {tol:g} (T={T})", kernel="stream_step_kernel", ms=best, bound="hbm", unit="GB/s",
+                achieved=alg / (best * 1e-3) / 1e9, peak=PEAK_HBM_GBS, frac=alg / (best * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                work=f"{alg:.4g} B over {T - 1} pushes", nnz=nnz)
+
+
+def counters_pass(ops, b, x0):
+    """One eager batched pass, then a plain 1 GiB device copy, for rocprofv3
+    --pmc runs: the copy's FETCH_SIZE / WRITE_SIZE calibrate the counters."""
+    import torch
+
+    bufs = b.buffers(x0)
+    ms = ops.pprviz_batch_profile(b, bufs, alpha=ALPHA, tol=TOL, stress_iters=STRESS_ITERS)
+    log(f"eager pass stage ms {ms}")
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+    torch.cuda.synchronize()
+    c.copy_(a)
+    torch.cuda.synchronize()
+    log("calibration copy: 1 GiB read, 1 GiB written")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +189,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the stage-timing pass")
+    ap.add_argument("--no-spmm", action="store_true", help="skip the streaming SpMM measurement")
+    ap.add_argument("--counters", action="store_true",
+                    help="one eager batched pass plus a 1 GiB calibration copy (for rocprofv3 --pmc), no timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1 "
@@ -134,6 +217,9 @@ def main():
     x0 = torch.as_tensor(synth.uniform_layout(b.n_nodes, synth.BASE_SEED + 99), device=dev)
     bufs = b.buffers(x0)
     T, _ = ops.pushes_for_tolerance(ALPHA, TOL, 100000)
+    if args.counters:
+        counters_pass(ops, b, x0)
+        return
     plan = ops.BatchPlan(b, bufs, alpha=ALPHA, tol=TOL, stress_iters=STRESS_ITERS)
     stream = torch.cuda.current_stream()
     for i in range(args.warmup):
@@ -159,33 +245,19 @@ def main():
     # ---- per-stage timing (HIP events recorded by the library on this stream)
     stages = None
     roof = None
-    n64 = sizes.astype(np.float64)
-    nnz = np.diff(gb.row_ptr.astype(np.int64))
-    arcs_per_graph = np.add.reduceat(nnz, gb.node_off[:-1].astype(np.int64)) if len(nnz) else np.zeros(G)
-    ppr_flops = float(((T - 1) * arcs_per_graph * n64).sum())   # one add per (arc, source) per push
-    layout_bytes = float((4.0 * n64 * n64 + 16.0 * n64).sum())  # Delta once + X in/out per sweep
     if not args.no_profile:
         bufs_p = b.buffers(x0)
         ms = ops.pprviz_batch_profile(b, bufs_p, alpha=ALPHA, tol=TOL, stress_iters=STRESS_ITERS)
         assert torch.equal(bufs_p["x_out"], bufs["x_out"]), "profiled run differs from the graph replay"
         del bufs_p
-        ppr_ms, layout_ms = ms[1], ms[3]
-        lay_launch_ms = layout_ms / (STRESS_ITERS + 1)
-        st_ppr = dict(kernel="batch_ppr_kernel", ms=ppr_ms, launches=1, bound="alu", unit="TFLOP/s",
-                      achieved=ppr_flops / (ppr_ms * 1e-3) / 1e12, peak=PEAK_FP32_TFLOPS,
-                      work=f"{ppr_flops:.4g} FP32 adds (one per arc, source and push)")
-        st_ppr["frac"] = st_ppr["achieved"] / PEAK_FP32_TFLOPS
-        st_lay = dict(kernel="batch_layout_kernel", ms=layout_ms, launches=STRESS_ITERS + 1, bound="hbm",
-                      unit="GB/s", achieved=layout_bytes / (lay_launch_ms * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
-                      work=f"{layout_bytes:.4g} B per sweep (Delta read once, X in and out)")
-        st_lay["frac"] = st_lay["achieved"] / PEAK_HBM_GBS
-        stages = dict(plan_ms=ms[0], ppr=st_ppr, pdist_ms=ms[2], layout=st_lay)
-        dom = st_ppr if ppr_ms >= layout_ms else st_lay
+        stages = stage_rooflines(gb, T, ms)
+        dom = stages["ppr"] if stages["ppr"]["ms"] >= stages["layout"]["ms"] else stages["layout"]
         traffic = traffic_from_profiles(dom["kernel"], f"sbm_batch_{G}")
         roof = dict(kernel=dom["kernel"], bound=dom["bound"], achieved=dom["achieved"], peak=dom["peak"],
                     unit=dom["unit"], frac=dom["frac"], traffic=traffic)
-        log(f"stages ms: plan {ms[0]:.2f} ppr {ppr_ms:.2f} pdist {ms[2]:.2f} layout {layout_ms:.2f}; "
-            f"ppr {st_ppr['achieved']:.2f} TFLOP/s, layout {st_lay['achieved']:.0f} GB/s")
+        log(f"stages ms: plan {ms[0]:.2f} ppr {ms[1]:.2f} pdist {ms[2]:.2f} layout {ms[3]:.2f}; "
+            f"ppr {stages['ppr']['achieved']:.0f} GB/s ({stages['ppr']['adds_per_s'] / 1e12:.2f} T adds/s), "
+            f"layout {stages['layout']['achieved']:.0f} GB/s")
 
     # ---- plain path: one subgraph at a time through the C ABI
     plain = None
@@ -241,6 +313,11 @@ def main():
             f"{value / plain['value']:.2f}x; identical={same}")
         del csrs
 
+    spmm = None
+    if not args.no_spmm:
+        spmm = spmm_stream(ops, dev)
+        log(f"streaming SpMM: {spmm['ms']:.1f} ms, {spmm['achieved']:.0f} GB/s algorithmic")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a sample ...")
@@ -269,6 +346,7 @@ def main():
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "roofline": roof,
         "stages": stages,
+        "spmm": spmm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

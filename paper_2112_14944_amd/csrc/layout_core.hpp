@@ -46,11 +46,12 @@ constexpr int kLayoutRowsPerBlock = 4 * kLayoutRowsPerWave;
 // layout_rows for the formulas).
 template <int MODE, bool INV>
 __device__ __forceinline__ void layout_pair(float Dv, bool off, float2 xi, float2 xj, float& ax, float& ay,
-                                            float& aw, float& as, bool acc_w, float scale, float* gd_ij) {
+                                            float& aw, float& as, float scale, float* gd_ij) {
     constexpr bool STEP = (MODE == kLayoutStep || MODE == kLayoutStepStress);
     constexpr bool STRESS = (MODE == kLayoutStepStress || MODE == kLayoutStress);
     constexpr bool GRAD = (MODE == kLayoutGradX || MODE == kLayoutGradBoth);
     constexpr bool WSUM = (MODE == kLayoutWsum);
+    constexpr bool acc_w = WSUM || (STEP && !INV);
     const float inv = INV ? Dv : (off ? __builtin_amdgcn_rcpf(Dv) : 0.f);
     const float w = inv * inv;
     if (acc_w) aw += w;
@@ -87,8 +88,9 @@ __device__ __forceinline__ void layout_pair(float Dv, bool off, float2 xi, float
 //   grad:   dL/dX_i = sum_j 2 w (d - Delta) (X_i - X_j)/d,
 //           dL/dDelta_ij = 2 (1 - d/Delta) d / Delta^2
 // INV: `delta` holds 1/Delta with a zero diagonal (precomputed once for many
-// sweeps) instead of Delta.  wsum: per-row sum_j w precomputed by the
-// kLayoutWsum pass (same summation order), or nullptr to accumulate it here.
+// sweeps) instead of Delta.  wsum: per-row sum_j w written by the kLayoutWsum
+// pass (same summation order); a step with INV reads it from there, a step
+// without INV accumulates it itself.
 // Full groups of 4 rows take a branch-free path that issues the loads of 4
 // columns (16 Delta values, 4 positions) before their arithmetic.
 // Returns this wave's stress contribution (lane 0 holds the wave total).
@@ -105,7 +107,6 @@ __device__ __forceinline__ double layout_rows(const float* __restrict__ delta, i
     constexpr bool WSUM = (MODE == kLayoutWsum);
     static_assert(!(INV && GRAD), "the gradient needs Delta itself");
     const int lane = threadIdx.x & 63;
-    const bool acc_w = WSUM || (STEP && wsum == nullptr);
     float2 xi[R];
     bool ok[R];
     float ax[R], ay[R], aw[R], as[R];
@@ -133,8 +134,7 @@ __device__ __forceinline__ double layout_rows(const float* __restrict__ delta, i
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int jj = j + u * kWave;
-                    layout_pair<MODE, INV>(dv[u][r], jj != row_begin + r, xi[r], xv[u], ax[r], ay[r], aw[r], as[r],
-                                           acc_w, scale,
+                    layout_pair<MODE, INV>(dv[u][r], jj != row_begin + r, xi[r], xv[u], ax[r], ay[r], aw[r], as[r], scale,
                                            GRAD ? gd + (int64_t)(row_begin + r) * ld + jj : nullptr);
                 }
             }
@@ -146,7 +146,7 @@ __device__ __forceinline__ double layout_rows(const float* __restrict__ delta, i
         for (int r = 0; r < R; ++r) {
             if (!ok[r]) continue;
             const int i = row_begin + r;
-            layout_pair<MODE, INV>(delta[(int64_t)i * ld + j], j != i, xi[r], xj, ax[r], ay[r], aw[r], as[r], acc_w,
+            layout_pair<MODE, INV>(delta[(int64_t)i * ld + j], j != i, xi[r], xj, ax[r], ay[r], aw[r], as[r],
                                    scale, GRAD ? gd + (int64_t)i * ld + j : nullptr);
         }
     }
@@ -163,7 +163,7 @@ __device__ __forceinline__ double layout_rows(const float* __restrict__ delta, i
             const float sx = wave_sum(ax[r]);
             const float sy = wave_sum(ay[r]);
             if (STEP) {
-                const float sw = wsum ? wsum[i] : wave_sum(aw[r]);
+                const float sw = INV ? wsum[i] : wave_sum(aw[r]);
                 if (lane == 0) xout[i] = sw > 0.f ? make_float2(sx / sw, sy / sw) : xi[r];
             } else if (gx && lane == 0) {
                 gx[i] = make_float2(scale * sx, scale * sy);
