@@ -15,11 +15,11 @@
 
 namespace pprviz {
 
-// One wave per arc: dq[e] = <A[u, :], pi[v, :]>; the last wave of each block
-// also handles the degree term of rows whose index equals an arc-block slot.
+// One wave per arc: dq[e] = <A[u, :], pi[v, :]>, A in the slab layout of
+// the streaming iterate, pi row-major n x n.
 __global__ __launch_bounds__(256) void arc_dot_kernel(const int32_t* __restrict__ row_of_arc,
                                                       const int32_t* __restrict__ col_idx, int64_t nnz,
-                                                      const float* __restrict__ A, int64_t lda,
+                                                      const float* __restrict__ A,
                                                       const float* __restrict__ pi, int32_t n,
                                                       double* __restrict__ dq) {
     const int lane = threadIdx.x & 63;
@@ -27,10 +27,9 @@ __global__ __launch_bounds__(256) void arc_dot_kernel(const int32_t* __restrict_
     if (e >= nnz) return;
     const int64_t u = row_of_arc[e];
     const int64_t v = col_idx[e];
-    const float* a = A + u * lda;
     const float* p = pi + v * (int64_t)n;
     double s = 0.0;
-    for (int t = lane; t < n; t += 64) s = fma((double)a[t], (double)p[t], s);
+    for (int t = lane; t < n; t += 64) s = fma((double)A[sidx(u, t, n)], (double)p[t], s);
     s = wave_sum(s);
     if (lane == 0) dq[e] = s;
 }
@@ -99,6 +98,7 @@ struct BwdWs {
     float* yb;
     float* pi;
     double* part;
+    int32_t* hist;
     double* dq;
     double* dd;
     double* g;
@@ -116,6 +116,7 @@ static void bwd_layout(Cursor& c, int n, int64_t nnz, bool recompute, BwdWs* w) 
     t.yb = c.template take<float>((size_t)n * ld);
     t.pi = recompute ? c.template take<float>((size_t)n * n) : nullptr;
     t.part = c.template take<double>((size_t)stream_resid_chunks(n) * ld);
+    t.hist = c.template take<int32_t>(kDegKeys);
     t.dq = c.template take<double>((size_t)std::max<int64_t>(nnz, 1));
     t.dd = c.template take<double>(n);
     t.g = c.template take<double>((size_t)std::max<int64_t>(nnz, 1));
@@ -143,7 +144,7 @@ ppr_status ppr_matrix_backward(const ppr_csr* g, float alpha, int32_t T, const f
     if (st != PPR_OK) return st;
     if (!(alpha > 0.0f && alpha < 1.0f) || T < 0 || grad_dppr == nullptr || (g->nnz > 0 && grad_arc == nullptr))
         return PPR_EINVAL;
-    if ((int64_t)g->n * g->n > ((int64_t)1 << 36)) return PPR_EUNSUPPORTED;
+    if ((int64_t)g->n * g->n > ((int64_t)1 << 36) || g->n > kStreamMaxN) return PPR_EUNSUPPORTED;
     const bool recompute = (ppr == nullptr);
     WsCursor cur{static_cast<char*>(ws), ws_bytes};
     BwdWs w;
@@ -156,11 +157,13 @@ ppr_status ppr_matrix_backward(const ppr_csr* g, float alpha, int32_t T, const f
     launch_degree(g->row_ptr, g->weight, n, w.deg, w.invd, s);
     const float* pi = ppr;
     if (recompute) {
-        ppr_forward(g, nullptr, n, nullptr, n, alpha, T, w.pi, nullptr, w.deg, w.invd, nullptr, w.rows, w.ya, w.yb,
-                    w.part, s);
+        ppr_forward(g, nullptr, n, nullptr, n, alpha, T, w.pi, nullptr, w.deg, w.invd, nullptr, w.rows, w.hist, w.ya,
+                    w.yb, w.part, s);
         pi = w.pi;
     }
+    stream_row_order(g->row_ptr, n, w.hist, w.rows, s);
     StreamArgs sa;
+    sa.rows = w.rows;
     sa.row_ptr = g->row_ptr;
     sa.col_idx = g->col_idx;
     sa.weight = g->weight;
@@ -176,7 +179,7 @@ ppr_status ppr_matrix_backward(const ppr_csr* g, float alpha, int32_t T, const f
     const float* A = stream_power_iteration(sa, T, w.ya, w.yb, s);
     hipLaunchKernelGGL(row_of_arc_kernel, dim3((n + 255) / 256), dim3(256), 0, s, g->row_ptr, n, w.row_of_arc);
     hipLaunchKernelGGL(arc_dot_kernel, dim3((unsigned)((g->nnz + 3) / 4)), dim3(256), 0, s, w.row_of_arc, g->col_idx,
-                       g->nnz, A, sa.ld, pi, n, w.dq);
+                       g->nnz, A, pi, n, w.dq);
     hipLaunchKernelGGL(row_dot_kernel, dim3((n + 3) / 4), dim3(256), 0, s, grad_dppr, pi, n, w.dd);
     hipLaunchKernelGGL(arc_grad_kernel, dim3((n + 255) / 256), dim3(256), 0, s, g->row_ptr, g->weight, w.deg, w.dq,
                        w.dd, n, alpha, w.g);

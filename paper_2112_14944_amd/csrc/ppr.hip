@@ -114,6 +114,7 @@ struct PprWs {
     float* ya;
     float* yb;
     double* part;
+    int32_t* hist;
 };
 
 ppr_status validate_csr(const ppr_csr* g) {
@@ -129,7 +130,7 @@ bool use_resident(int n) { return res_cols_for(n) != 0; }
 // the LDS-resident kernel.
 void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int32_t* tgt, int32_t n_tgt,
                  float alpha, int32_t T, float* ppr_out, float* dppr_out, const float* deg, const float* invd,
-                 double* resid, RowEnt* rows, float* ya, float* yb, double* part, hipStream_t s) {
+                 double* resid, RowEnt* rows, int32_t* hist, float* ya, float* yb, double* part, hipStream_t s) {
     const int n = g->n;
     if (use_resident(n)) {
         launch_row_table(g->row_ptr, nullptr, n, 1, rows, s);
@@ -154,7 +155,9 @@ void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int3
             default: launch_resident<16>(wt, a, n, n_src, n_tgt, s); break;
         }
     } else {
+        stream_row_order(g->row_ptr, n, hist, rows, s);
         StreamArgs sa;
+        sa.rows = rows;
         sa.row_ptr = g->row_ptr;
         sa.col_idx = g->col_idx;
         sa.weight = g->weight;
@@ -186,16 +189,19 @@ static void ppr_ws_layout(Cursor& c, int n, int n_src, PprWs* w) {
         w->resid = resid;
         w->ya = w->yb = nullptr;
         w->part = nullptr;
+        w->hist = nullptr;
     }
     if (!use_resident(n)) {
         const int64_t ldy = stream_ld(n_src);
         auto* ya = c.template take<float>((size_t)n * ldy);
         auto* yb = c.template take<float>((size_t)n * ldy);
         auto* part = c.template take<double>((size_t)stream_resid_chunks(n) * ldy);
+        auto* hist = c.template take<int32_t>(kDegKeys);
         if (w) {
             w->ya = ya;
             w->yb = yb;
             w->part = part;
+            w->hist = hist;
         }
     }
 }
@@ -269,6 +275,7 @@ ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src, const
     if (tgt == nullptr && n_tgt != g->n) return PPR_EINVAL;
     if (!(alpha > 0.0f && alpha < 1.0f) || max_iter < 0) return PPR_EINVAL;
     if ((int64_t)n_src * (int64_t)std::max(n_tgt, 1) > ((int64_t)1 << 40)) return PPR_EUNSUPPORTED;
+    if (!use_resident(g->n) && g->n > kStreamMaxN) return PPR_EUNSUPPORTED;
     int32_t T = 0, conv = 1;
     st = pprviz_pushes_for_tolerance(alpha, tol_l1, max_iter, &T, &conv);
     if (st != PPR_OK) return st;
@@ -283,8 +290,8 @@ ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src, const
     const int n = g->n;
     launch_degree(g->row_ptr, g->weight, n, w.deg, w.invd, s);
 
-    ppr_forward(g, src, n_src, tgt, n_tgt, alpha, T, ppr_out, dppr_out, w.deg, w.invd, w.resid, w.rows, w.ya, w.yb,
-                w.part, s);
+    ppr_forward(g, src, n_src, tgt, n_tgt, alpha, T, ppr_out, dppr_out, w.deg, w.invd, w.resid, w.rows, w.hist, w.ya,
+                w.yb, w.part, s);
     st = launch_status();
     if (st != PPR_OK) return st;
     if (resid_out) {

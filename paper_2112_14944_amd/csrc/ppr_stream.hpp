@@ -9,7 +9,7 @@
 // which gathers over the same neighbours with the same coefficients.
 #pragma once
 
-#include "common.hpp"
+#include "ppr_core.hpp"
 
 namespace pprviz {
 
@@ -17,7 +17,19 @@ inline int64_t stream_ld(int64_t ncols) { return (ncols + 63) / 64 * 64; }
 constexpr int kStreamResidRows = 4096;
 inline int64_t stream_resid_chunks(int64_t n) { return (n + kStreamResidRows - 1) / kStreamResidRows; }
 
+// Iterate layout: column slabs of 32 columns, each slab stored node-major
+// and contiguous (n rows of 128 bytes), slab after slab; ld columns in all
+// (ld a multiple of 64), so a buffer holds n * ld floats.
+constexpr int kSlab = 32;
+constexpr int kSlabVec = kSlab / 4;             // float4 per slab row
+constexpr int kArcsPerLoad = kWave / kSlabVec;  // arcs one wave load covers
+
+__host__ __device__ __forceinline__ int64_t sidx(int64_t v, int64_t col, int64_t n) {
+    return ((col / kSlab) * n + v) * kSlab + (col % kSlab);
+}
+
 struct StreamArgs {
+    const RowEnt* rows;   // rows by non-increasing degree (stream_row_order)
     const int32_t* row_ptr;
     const int32_t* col_idx;
     const float* weight;
@@ -25,89 +37,211 @@ struct StreamArgs {
     const float* deg;
     int32_t n;
     int32_t ncols;        // valid columns (sources / adjoint right-hand sides)
-    int64_t ld;           // leading dimension of the iterate (multiple of 64)
+    int64_t ld;           // columns held (multiple of 64)
     float alpha;
     const int32_t* src;   // forward: source node of column s (nullptr: column s = node s)
     const float* forcing; // adjoint: G [n][ld_forcing] (Gb = deg[v] * G[v][s]); nullptr = forward
     int64_t ld_forcing;
 };
 
-constexpr int kStreamRowsPerWave = 4;
+constexpr int kStreamRowsPerWave = kWave / kSlabVec;  // 8 rows side by side
 constexpr int kStreamRowsPerBlock = 4 * kStreamRowsPerWave;
+constexpr int kXcds = 8;
+// A slab of the iterate that fits this budget stays in one XCD's L2 (4 MB)
+// next to the arc stream while that XCD sweeps it.
+constexpr int64_t kStreamSlabBudget = 3 << 20;
+constexpr int kDegKeys = 4096;
+// Slab gathers use 32-bit byte offsets: n * 128 must stay below 2^31.
+constexpr int32_t kStreamMaxN = 1 << 24;  // degree classes of the row order (exact below 4095)
 
-// MODE 0: forward (forcing alpha at the source row); MODE 1: adjoint.
+// Launch shape of one push: `slabs` column slabs, each swept by `row_blocks`
+// blocks of 32 rows.
+struct StreamGrid {
+    int32_t row_blocks;
+    int32_t slabs;
+    int32_t full_rounds;  // rounds of 8 slabs run one per XCD (0: none)
+};
+
+// Block -> (slab, row block).  Workgroups go to the 8 XCDs round-robin by
+// linear id, so blocks b, b + 8, b + 16, ... share one XCD.  In each of the
+// first full_rounds rounds every XCD sweeps all rows of a slab of its own, so
+// the neighbour rows it gathers are served by its own L2.  The remaining
+// slabs are taken one after another by all XCDs together (for large n that
+// keeps one slab at a time in the shared last-level cache).  The grid has
+// exactly slabs * row_blocks blocks and the map is a bijection onto the pairs.
+__device__ __forceinline__ void stream_block_map(const StreamGrid& g, int& slab, int& rb) {
+    const int b = blockIdx.x;
+    const int full_blocks = g.full_rounds * kXcds * g.row_blocks;
+    if (b < full_blocks) {
+        const int local = b / kXcds;
+        slab = (local / g.row_blocks) * kXcds + b % kXcds;
+        rb = local % g.row_blocks;
+    } else {
+        const int local = b - full_blocks;
+        slab = g.full_rounds * kXcds + local / g.row_blocks;
+        rb = local % g.row_blocks;
+    }
+}
+
+// Row order for the streaming step: a counting sort of the rows by degree,
+// largest first, so the 8 rows a wave takes side by side have (nearly) equal
+// arc counts.  The order within a degree class is whatever the atomics give;
+// it only decides which rows share a wave, never a sum.
+static __global__ void stream_deg_hist_kernel(const int32_t* __restrict__ row_ptr, int32_t n,
+                                              int32_t* __restrict__ hist) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int d = min(row_ptr[v + 1] - row_ptr[v], kDegKeys - 1);
+    atomicAdd(&hist[kDegKeys - 1 - d], 1);
+}
+
+// Exclusive prefix sum of the kDegKeys class counts, in place (one block).
+static __global__ __launch_bounds__(256) void stream_deg_scan_kernel(int32_t* __restrict__ hist) {
+    constexpr int kPer = kDegKeys / 256;
+    __shared__ int32_t part[256];
+    int32_t loc[kPer];
+    int32_t t = 0;
+    for (int i = 0; i < kPer; ++i) {
+        loc[i] = t;
+        t += hist[threadIdx.x * kPer + i];
+    }
+    part[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int32_t x = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += x;
+        __syncthreads();
+    }
+    const int32_t base = part[threadIdx.x] - t;
+    for (int i = 0; i < kPer; ++i) hist[threadIdx.x * kPer + i] = base + loc[i];
+}
+
+static __global__ void stream_deg_scatter_kernel(const int32_t* __restrict__ row_ptr, int32_t n,
+                                                 int32_t* __restrict__ cursor, RowEnt* __restrict__ rows) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int rs = row_ptr[v], re = row_ptr[v + 1];
+    const int d = min(re - rs, kDegKeys - 1);
+    const int pos = atomicAdd(&cursor[kDegKeys - 1 - d], 1);
+    rows[pos] = RowEnt{rs, re, (int32_t)v, 0};
+}
+
+inline void stream_row_order(const int32_t* row_ptr, int32_t n, int32_t* hist, RowEnt* rows, hipStream_t s) {
+    fill<int32_t>(hist, 0, kDegKeys, s);
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(stream_deg_hist_kernel, dim3(blocks), dim3(256), 0, s, row_ptr, n, hist);
+    hipLaunchKernelGGL(stream_deg_scan_kernel, dim3(1), dim3(256), 0, s, hist);
+    hipLaunchKernelGGL(stream_deg_scatter_kernel, dim3(blocks), dim3(256), 0, s, row_ptr, n, hist, rows);
+}
+
+__device__ __forceinline__ void f4_acc(float4& a, float4 y) {
+    a.x += y.x;
+    a.y += y.y;
+    a.z += y.z;
+    a.w += y.w;
+}
+
+__device__ __forceinline__ void f4_fma(float4& a, float w, float4 y) {
+    a.x = fmaf(w, y.x, a.x);
+    a.y = fmaf(w, y.y, a.y);
+    a.z = fmaf(w, y.z, a.z);
+    a.w = fmaf(w, y.w, a.w);
+}
+
+// Gather of one 16-byte piece of a slab row through a buffer resource: an
+// offset past the slab (a padded arc slot) reads zeros and touches no memory.
+__device__ __forceinline__ float4 slab_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+    return make_float4(__int_as_float(v[0]), __int_as_float(v[1]), __int_as_float(v[2]), __int_as_float(v[3]));
+}
+
+// One push (MODE 0: forward, forcing alpha at each column's source row;
+// MODE 1: adjoint, forcing deg[v] * G[v][col]).  A wave takes 8 rows of the
+// degree order side by side within one slab: lane = 8 * g + q, where g picks
+// the row and q 4 of the slab's 32 columns (one 16-byte load per arc).  The
+// group's lanes read 8 arc indices at once, coalesced, and pass them round
+// with ds_bpermute; each lane then sums its row's neighbours in arc order,
+// so a row's result does not depend on which rows share its wave.
 template <int MODE, bool WEIGHTED, bool FINAL>
 __global__ __launch_bounds__(256) void stream_step_kernel(
-    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+    const RowEnt* __restrict__ rows, const int32_t* __restrict__ col_idx,
     const float* __restrict__ weight, const float* __restrict__ invd, const float* __restrict__ deg,
     const int32_t* __restrict__ src, const float* __restrict__ forcing, int64_t ld_forcing, int32_t n,
-    int32_t ncols, int64_t ld, float alpha, const float* __restrict__ yin, float* __restrict__ yout) {
+    int32_t ncols, float alpha, StreamGrid grid, const float* __restrict__ yin, float* __restrict__ yout) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t col = (int64_t)blockIdx.y * 64 + lane;
-    const bool valid = col < ncols;
-    int my_src = -1;
-    if (MODE == 0 && valid) my_src = src ? src[col] : (int)col;
-    const float oma = 1.0f - alpha;
-    const int v0 = blockIdx.x * kStreamRowsPerBlock + wave * kStreamRowsPerWave;
-    for (int r = 0; r < kStreamRowsPerWave; ++r) {
-        const int v = __builtin_amdgcn_readfirstlane(v0 + r);
-        if (v >= n) return;
-        const int rs = row_ptr[v];
-        const int re = row_ptr[v + 1];
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-        if (rs == re) a0 = yin[(int64_t)v * ld + col];
-        int e = rs;
-        for (; e + 8 <= re; e += 8) {
-            const int64_t u0 = col_idx[e + 0], u1 = col_idx[e + 1], u2 = col_idx[e + 2], u3 = col_idx[e + 3];
-            const int64_t u4 = col_idx[e + 4], u5 = col_idx[e + 5], u6 = col_idx[e + 6], u7 = col_idx[e + 7];
-            const float y0 = yin[u0 * ld + col], y1 = yin[u1 * ld + col], y2 = yin[u2 * ld + col],
-                        y3 = yin[u3 * ld + col];
-            const float y4 = yin[u4 * ld + col], y5 = yin[u5 * ld + col], y6 = yin[u6 * ld + col],
-                        y7 = yin[u7 * ld + col];
+    const int q = lane % kSlabVec;
+    int slab, rb;
+    stream_block_map(grid, slab, rb);
+    const int64_t slab_off = (int64_t)slab * n * kSlab;
+    const uint32_t slab_bytes = (uint32_t)n * (kSlab * 4);
+    const __amdgpu_buffer_rsrc_t rin =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(yin + slab_off), 0, (int)slab_bytes, 0x00020000);
+    const int ri = rb * kStreamRowsPerBlock + wave * kStreamRowsPerWave + lane / kSlabVec;
+    const bool has_row = ri < n;
+    int rs = 0, dg = 0, v = 0;
+    if (has_row) {
+        const RowEnt e = load_row(as_global(rows), ri);
+        rs = e.rs;
+        dg = e.re - e.rs;
+        v = e.v;
+    }
+    int dmax = dg;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, kWave));
+    const uint32_t qoff = (uint32_t)q * 16u;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (has_row && dg == 0) acc = slab_load(rin, ((uint32_t)v << 7) | qoff);
+    const int lead = (lane & ~(kSlabVec - 1)) * 4;  // ds_bpermute address of the group's first lane
+    for (int k0 = 0; k0 < dmax; k0 += kSlabVec) {
+        const bool ok = k0 + q < dg;
+        const int idx = ok ? col_idx[rs + k0 + q] : -1;
+        float wl = 0.f;
+        if (WEIGHTED) wl = ok ? weight[rs + k0 + q] : 0.f;
+        float4 y[kSlabVec];
+#pragma unroll
+        for (int j = 0; j < kSlabVec; ++j) {
+            const int u = __builtin_amdgcn_ds_bpermute(lead + 4 * j, idx);
+            y[j] = slab_load(rin, ((uint32_t)u << 7) | qoff);
+        }
+#pragma unroll
+        for (int j = 0; j < kSlabVec; ++j) {
             if (WEIGHTED) {
-                a0 = fmaf(weight[e + 0], y0, a0);
-                a1 = fmaf(weight[e + 1], y1, a1);
-                a2 = fmaf(weight[e + 2], y2, a2);
-                a3 = fmaf(weight[e + 3], y3, a3);
-                a0 = fmaf(weight[e + 4], y4, a0);
-                a1 = fmaf(weight[e + 5], y5, a1);
-                a2 = fmaf(weight[e + 6], y6, a2);
-                a3 = fmaf(weight[e + 7], y7, a3);
+                const float w = __int_as_float(__builtin_amdgcn_ds_bpermute(lead + 4 * j, __float_as_int(wl)));
+                f4_fma(acc, w, y[j]);
             } else {
-                a0 += y0;
-                a1 += y1;
-                a2 += y2;
-                a3 += y3;
-                a0 += y4;
-                a1 += y5;
-                a2 += y6;
-                a3 += y7;
+                f4_acc(acc, y[j]);
             }
         }
-        for (; e < re; ++e) {
-            const int64_t u = col_idx[e];
-            const float y = yin[u * ld + col];
-            if (WEIGHTED) a0 = fmaf(weight[e], y, a0); else a0 += y;
-        }
-        float x = (a0 + a1) + (a2 + a3);
-        if (MODE == 0) {
-            x += (v == my_src) ? alpha : 0.0f;
-        } else {
-            x += valid ? deg[v] * forcing[(int64_t)v * ld_forcing + col] : 0.0f;
-        }
-        yout[(int64_t)v * ld + col] = FINAL ? x : x * oma * invd[v];
     }
+    if (!has_row) return;
+    const int col0 = slab * kSlab + q * 4;
+    float x[4] = {acc.x, acc.y, acc.z, acc.w};
+    const float sv = FINAL ? 1.0f : (1.0f - alpha) * invd[v];
+    const float dv = MODE == 1 ? deg[v] : 0.f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int col = col0 + c;
+        if (MODE == 0) {
+            if (col < ncols && v == (src ? src[col] : col)) x[c] += alpha;
+        } else {
+            x[c] += col < ncols ? dv * forcing[(int64_t)v * ld_forcing + col] : 0.0f;
+        }
+        x[c] = FINAL ? x[c] : x[c] * sv;
+    }
+    float4* o4 = reinterpret_cast<float4*>(yout + slab_off);
+    o4[(int64_t)v * kSlabVec + q] = make_float4(x[0], x[1], x[2], x[3]);
 }
 
 // Y_0 for the forward iteration: zero everywhere but the source rows.
 static __global__ void stream_init_forward_kernel(const int32_t* __restrict__ src, const float* __restrict__ invd,
-                                           int32_t ncols, int64_t ld, float alpha, int final_,
+                                           int32_t n, int32_t ncols, float alpha, int final_,
                                            float* __restrict__ y) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= ncols) return;
     int v = src ? src[s] : s;
-    y[(int64_t)v * ld + s] = final_ ? alpha : alpha * (1.0f - alpha) * invd[v];
+    y[sidx(v, s, n)] = final_ ? alpha : alpha * (1.0f - alpha) * invd[v];
 }
 
 // Y_0 = (1-alpha)/d * Gb for the adjoint (Gb = d * G), or Gb itself when final.
@@ -119,12 +253,12 @@ static __global__ void stream_init_adjoint_kernel(const float* __restrict__ forc
     const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (v >= n) return;
     float g = col < ncols ? deg[v] * forcing[v * ld_forcing + col] : 0.0f;
-    y[v * ld + col] = final_ ? g : g * (1.0f - alpha) * invd[v];
+    y[sidx(v, col, n)] = final_ ? g : g * (1.0f - alpha) * invd[v];
 }
 
 // out[s][j] = X[tgt[j]][s] (and d(src_s) times it), 64x64 tiles through LDS.
 static __global__ __launch_bounds__(256) void stream_transpose_kernel(
-    const float* __restrict__ x, int64_t ld, int32_t ncols, const int32_t* __restrict__ src,
+    const float* __restrict__ x, int32_t n, int32_t ncols, const int32_t* __restrict__ src,
     const int32_t* __restrict__ tgt, int32_t n_tgt, const float* __restrict__ deg,
     float* __restrict__ ppr_out, float* __restrict__ dppr_out, int64_t ld_out) {
     __shared__ float tile[64][65];
@@ -137,7 +271,7 @@ static __global__ __launch_bounds__(256) void stream_transpose_kernel(
         float val = 0.f;
         if (j < n_tgt) {
             const int64_t tn = tgt ? tgt[j] : j;
-            val = x[tn * ld + s0 + lane];
+            val = x[sidx(tn, s0 + lane, n)];
         }
         tile[jj][lane] = val;
     }
@@ -166,7 +300,7 @@ static __global__ __launch_bounds__(256) void stream_colsum_kernel(const float* 
     const int64_t r0 = (int64_t)blockIdx.x * kStreamResidRows;
     const int64_t r1 = min((int64_t)n, r0 + kStreamResidRows);
     double s = 0.0;
-    for (int64_t r = r0 + w; r < r1; r += 4) s += (double)x[r * ld + col];
+    for (int64_t r = r0 + w; r < r1; r += 4) s += (double)x[sidx(r, col, n)];
     red[w][lane] = s;
     __syncthreads();
     if (w == 0) part[(int64_t)blockIdx.x * ld + col] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
@@ -183,15 +317,19 @@ static __global__ void stream_resid_kernel(const double* __restrict__ part, int6
 
 template <int MODE, bool FINAL>
 inline void stream_launch_step(const StreamArgs& a, const float* yin, float* yout, hipStream_t s) {
-    dim3 grid((unsigned)((a.n + kStreamRowsPerBlock - 1) / kStreamRowsPerBlock), (unsigned)(a.ld / 64));
+    StreamGrid g;
+    g.row_blocks = (a.n + kStreamRowsPerBlock - 1) / kStreamRowsPerBlock;
+    g.slabs = (int32_t)(a.ld / kSlab);
+    g.full_rounds = ((int64_t)a.n * kSlab * 4 <= kStreamSlabBudget) ? g.slabs / kXcds : 0;
+    const dim3 grid((unsigned)((int64_t)g.row_blocks * g.slabs));
     if (a.weight)
-        hipLaunchKernelGGL((stream_step_kernel<MODE, true, FINAL>), grid, dim3(256), 0, s, a.row_ptr, a.col_idx,
-                           a.weight, a.invd, a.deg, a.src, a.forcing, a.ld_forcing, a.n, a.ncols, a.ld, a.alpha,
-                           yin, yout);
+        hipLaunchKernelGGL((stream_step_kernel<MODE, true, FINAL>), grid, dim3(256), 0, s, a.rows, a.col_idx,
+                           a.weight, a.invd, a.deg, a.src, a.forcing, a.ld_forcing, a.n, a.ncols, a.alpha, g, yin,
+                           yout);
     else
-        hipLaunchKernelGGL((stream_step_kernel<MODE, false, FINAL>), grid, dim3(256), 0, s, a.row_ptr, a.col_idx,
-                           a.weight, a.invd, a.deg, a.src, a.forcing, a.ld_forcing, a.n, a.ncols, a.ld, a.alpha,
-                           yin, yout);
+        hipLaunchKernelGGL((stream_step_kernel<MODE, false, FINAL>), grid, dim3(256), 0, s, a.rows, a.col_idx,
+                           a.weight, a.invd, a.deg, a.src, a.forcing, a.ld_forcing, a.n, a.ncols, a.alpha, g, yin,
+                           yout);
 }
 
 // T pushes (forward, a.forcing == nullptr) or T adjoint terms; returns the
@@ -207,7 +345,7 @@ inline const float* stream_power_iteration(const StreamArgs& a, int T, float* ya
                            a.invd, a.n, a.ncols, a.ld, a.alpha, T == 1 ? 1 : 0, ya);
     } else {
         hipLaunchKernelGGL(stream_init_forward_kernel, dim3((a.ncols + 255) / 256), dim3(256), 0, s, a.src,
-                           a.invd, a.ncols, a.ld, a.alpha, T == 1 ? 1 : 0, ya);
+                           a.invd, a.n, a.ncols, a.alpha, T == 1 ? 1 : 0, ya);
     }
     float* in = ya;
     float* out = yb;
@@ -229,7 +367,7 @@ inline void stream_write_outputs(const float* x, const StreamArgs& a, const int3
                                  float* ppr_out, float* dppr_out, hipStream_t s) {
     if (!ppr_out && !dppr_out) return;
     dim3 grid((unsigned)((n_tgt + 63) / 64), (unsigned)((a.ncols + 63) / 64));
-    hipLaunchKernelGGL(stream_transpose_kernel, grid, dim3(256), 0, s, x, a.ld, a.ncols, a.src, tgt, n_tgt, a.deg,
+    hipLaunchKernelGGL(stream_transpose_kernel, grid, dim3(256), 0, s, x, a.n, a.ncols, a.src, tgt, n_tgt, a.deg,
                        ppr_out, dppr_out, (int64_t)n_tgt);
 }
 
