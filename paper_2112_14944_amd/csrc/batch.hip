@@ -11,8 +11,10 @@
 //            (subgraph, source tile) tasks from an atomic counter in LPT order
 //            and run the LDS-resident power iteration of ppr_core.hpp.
 //  pdist     grid-stride over (subgraph, 64x64 tile) items.
-//  layout    stress_iters launches, each grid-stride over (subgraph, 16-row
-//            block) items; then one stress pass of the final layout.
+//  layout    the row sums of Delta^-2 (one pass), then stress_iters sweep
+//            launches that pop (subgraph, 16-row block) items, largest
+//            subgraphs first, from per-XCD queues; then one stress pass of
+//            the final layout.
 #include <math.h>
 
 #include <algorithm>
@@ -25,6 +27,7 @@ namespace pprviz {
 
 constexpr int kBatchMaxN = Res<16>::NMAX;  // 2304
 constexpr int kPlanThreads = 1024;
+constexpr int kXcdQueues = 8;
 
 struct BatchPlan {
     int32_t* order;      // [G] subgraph ids, largest first
@@ -33,6 +36,9 @@ struct BatchPlan {
     int64_t* rb_pre;     // [G+1] prefix of 16-row layout blocks (subgraph order)
     int32_t* pd_graph;   // subgraph of each PDist tile item
     int32_t* rb_graph;   // subgraph of each layout row-block item
+    int64_t* rl_pre;     // [G+1] prefix of 16-row layout blocks in LPT order
+    int64_t* rl_start;   // [G] first LPT item of each subgraph
+    int32_t* rl_graph;   // subgraph of each layout row-block item in LPT order
     int32_t* counter;    // [3] PPR task queue heads, one per tile width
     int32_t* cls_pos;    // [4] first LPT position of the 16-, 32- and 64-column classes, then G
 };
@@ -83,14 +89,16 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t*
     }
     __syncthreads();
     __threadfence_block();
-    // three prefix sums (sequential chunks per thread, then a block scan)
-    for (int which = 0; which < 3; ++which) {
-        int64_t* out = which == 0 ? p.tile_pre : (which == 1 ? p.pd_pre : p.rb_pre);
+    // four prefix sums (sequential chunks per thread, then a block scan):
+    // PPR tiles in LPT order, PDist tiles and layout row blocks in subgraph
+    // order, layout row blocks in LPT order
+    for (int which = 0; which < 4; ++which) {
+        int64_t* out = which == 0 ? p.tile_pre : (which == 1 ? p.pd_pre : (which == 2 ? p.rb_pre : p.rl_pre));
         const int per = (G + kPlanThreads - 1) / kPlanThreads;
         const int a = tid * per, b = min(G, a + per);
         int64_t loc = 0;
         for (int i = a; i < b; ++i) {
-            const int g = which == 0 ? p.order[i] : i;
+            const int g = (which == 0 || which == 3) ? p.order[i] : i;
             const int n = graph_n(node_off, g);
             loc += which == 0 ? tiles_of(n) : (which == 1 ? (int64_t)((n + 63) / 64) * ((n + 63) / 64)
                                                           : (int64_t)((n + kLayoutRowsPerBlock - 1) / kLayoutRowsPerBlock));
@@ -109,7 +117,7 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t*
         int64_t run = scan_tmp[tid];
         for (int i = a; i < b; ++i) {
             out[i] = run;
-            const int g = which == 0 ? p.order[i] : i;
+            const int g = (which == 0 || which == 3) ? p.order[i] : i;
             const int n = graph_n(node_off, g);
             run += which == 0 ? tiles_of(n) : (which == 1 ? (int64_t)((n + 63) / 64) * ((n + 63) / 64)
                                                           : (int64_t)((n + kLayoutRowsPerBlock - 1) / kLayoutRowsPerBlock));
@@ -121,6 +129,11 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t*
     for (int g = tid; g < G; g += kPlanThreads) {
         for (int64_t i = p.pd_pre[g]; i < p.pd_pre[g + 1]; ++i) p.pd_graph[i] = g;
         for (int64_t i = p.rb_pre[g]; i < p.rb_pre[g + 1]; ++i) p.rb_graph[i] = g;
+    }
+    for (int pos = tid; pos < G; pos += kPlanThreads) {
+        const int g = p.order[pos];
+        p.rl_start[g] = p.rl_pre[pos];
+        for (int64_t i = p.rl_pre[pos]; i < p.rl_pre[pos + 1]; ++i) p.rl_graph[i] = g;
     }
     // Sizes are sorted descending, so each tile width owns a contiguous range
     // of positions: n > Res<32>::NMAX (16 columns), then n > Res<64>::NMAX
@@ -223,12 +236,17 @@ __global__ __launch_bounds__(256) void batch_pdist_kernel(const int64_t* __restr
     }
 }
 
-// Layout row blocks of every subgraph, grid-stride over (subgraph, 16 rows).
+// Layout row blocks of every subgraph, grid-stride over (subgraph, 16 rows)
+// items.  item_graph / graph_start give each item's subgraph and the first
+// item of that subgraph: subgraph order (rb_graph, rb_pre) where the item
+// index also names a stress partial, largest subgraphs first (rl_graph,
+// rl_start) for the sweeps, so that the blocks' shares come out even.
 template <int MODE>
 __global__ __launch_bounds__(256) void batch_layout_kernel(const int64_t* __restrict__ node_off,
                                                            const int64_t* __restrict__ mat_off, int32_t G,
                                                            const int64_t* __restrict__ rb_pre,
-                                                           const int32_t* __restrict__ rb_graph,
+                                                           const int32_t* __restrict__ item_graph,
+                                                           const int64_t* __restrict__ graph_start,
                                                            const float* __restrict__ inv,
                                                            const float2* __restrict__ x, float2* __restrict__ xout,
                                                            float* __restrict__ wsum, double* __restrict__ part) {
@@ -236,9 +254,9 @@ __global__ __launch_bounds__(256) void batch_layout_kernel(const int64_t* __rest
     const int wave = threadIdx.x >> 6;
     const int64_t total = rb_pre[G];
     for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-        const int g = rb_graph[item];
+        const int g = item_graph[item];
         const int k = graph_n(node_off, g);
-        const int64_t rb = item - rb_pre[g];
+        const int64_t rb = item - graph_start[g];
         const int64_t nb = node_off[g];
         const int row_begin = (int)(rb * kLayoutRowsPerBlock) + wave * kLayoutRowsPerWave;
         const double st = layout_rows<MODE, true>(inv + mat_off[g], k, k, x + nb, row_begin,
@@ -249,6 +267,49 @@ __global__ __launch_bounds__(256) void batch_layout_kernel(const int64_t* __rest
             __syncthreads();
             if (threadIdx.x == 0) part[item] = (red[0] + red[1]) + (red[2] + red[3]);
             __syncthreads();
+        }
+    }
+}
+
+// Queue heads of one sweep: one per XCD, each on its own 128-byte line.
+constexpr int kQueueStride = 32;
+constexpr int kQueueInts = 2 * kXcdQueues * kQueueStride;  // two sweeps' worth
+
+// One Jacobi sweep over all subgraphs with dynamic scheduling.  Items (16
+// rows of one subgraph) are in LPT order and dealt round-robin into 8 queues;
+// a block drains the queue of its own XCD (blocks go to XCDs round-robin by
+// id) and then helps with the others.  Which block takes an item does not
+// change any result.  The launch also clears the heads the next sweep will
+// use (q_next), which the previous sweep finished with.
+__global__ __launch_bounds__(256) void batch_sweep_kernel(const int64_t* __restrict__ node_off,
+                                                          const int64_t* __restrict__ mat_off, int32_t G,
+                                                          const int64_t* __restrict__ rb_pre,
+                                                          const int32_t* __restrict__ rl_graph,
+                                                          const int64_t* __restrict__ rl_start,
+                                                          const float* __restrict__ inv,
+                                                          const float2* __restrict__ x, float2* __restrict__ xout,
+                                                          float* __restrict__ wsum, int32_t* __restrict__ q_cur,
+                                                          int32_t* __restrict__ q_next) {
+    __shared__ int64_t s_item;
+    const int wave = threadIdx.x >> 6;
+    if (blockIdx.x == 0 && threadIdx.x < kXcdQueues) q_next[threadIdx.x * kQueueStride] = 0;
+    const int64_t total = rb_pre[G];
+    const int home = blockIdx.x % kXcdQueues;
+    for (int t = 0; t < kXcdQueues; ++t) {
+        const int qid = (home + t) % kXcdQueues;
+        for (;;) {
+            if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(&q_cur[qid * kQueueStride], 1) * kXcdQueues + qid;
+            __syncthreads();
+            const int64_t item = s_item;
+            __syncthreads();
+            if (item >= total) break;
+            const int g = rl_graph[item];
+            const int k = graph_n(node_off, g);
+            const int64_t rb = item - rl_start[g];
+            const int64_t nb = node_off[g];
+            const int row_begin = (int)(rb * kLayoutRowsPerBlock) + wave * kLayoutRowsPerWave;
+            layout_rows<kLayoutStep, true>(inv + mat_off[g], k, k, x + nb, row_begin, xout + nb, 1.f, nullptr,
+                                           nullptr, wsum + nb);
         }
     }
 }
@@ -277,6 +338,7 @@ struct BatchWs {
     float* wsum;  // per node sum_j Delta^-2
     float* xtmp;
     double* part;
+    int32_t* queues;  // sweep queue heads, two sweeps' worth
     BatchPlan plan;
 };
 
@@ -291,6 +353,7 @@ static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     t.xtmp = c.template take<float>((size_t)b->n_nodes * 2);
     // row blocks: sum over g of ceil(n_g/16) <= n_nodes/16 + G
     t.part = c.template take<double>((size_t)(b->n_nodes / kLayoutRowsPerBlock + b->n_graphs + 1));
+    t.queues = c.template take<int32_t>(kQueueInts);
     t.plan.order = c.template take<int32_t>((size_t)b->n_graphs);
     t.plan.tile_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
     t.plan.pd_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
@@ -299,6 +362,9 @@ static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     // sum_g ceil(n_g/16) <= n_nodes/16 + G
     t.plan.pd_graph = c.template take<int32_t>((size_t)(b->pool_size / 4096 + b->n_nodes / 32 + b->n_graphs + 1));
     t.plan.rb_graph = c.template take<int32_t>((size_t)(b->n_nodes / kLayoutRowsPerBlock + b->n_graphs + 1));
+    t.plan.rl_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
+    t.plan.rl_start = c.template take<int64_t>((size_t)b->n_graphs);
+    t.plan.rl_graph = c.template take<int32_t>((size_t)(b->n_nodes / kLayoutRowsPerBlock + b->n_graphs + 1));
     t.plan.counter = c.template take<int32_t>(64);
     t.plan.cls_pos = c.template take<int32_t>(64);
     if (w) *w = t;
@@ -359,11 +425,13 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     hipLaunchKernelGGL((batch_ppr_kernel<64, 2>), dim3(cus), dim3(kResThreads), 0, s, ba, w.plan);
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[2], s));
 
-    const unsigned grid = (unsigned)cus * 16;
+    // 8 blocks of 4 waves per CU: every block resident at once
+    const unsigned grid = (unsigned)cus * 8;
     hipLaunchKernelGGL(batch_pdist_kernel, dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off, G, w.plan.pd_pre,
                        w.plan.pd_graph, dppr_pool, delta_pool, w.inv);
     hipLaunchKernelGGL((batch_layout_kernel<kLayoutWsum>), dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off, G,
-                       w.plan.rb_pre, w.plan.rb_graph, w.inv, reinterpret_cast<const float2*>(x0), nullptr, w.wsum,
+                       w.plan.rb_pre, w.plan.rb_graph, w.plan.rb_pre, w.inv, reinterpret_cast<const float2*>(x0),
+                       nullptr, w.wsum,
                        nullptr);
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[3], s));
 
@@ -375,16 +443,20 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
         hipLaunchKernelGGL(copy_kernel, dim3(1024), dim3(256), 0, s, x0, x_out, b->n_nodes * 2);
         cur = reinterpret_cast<const float2*>(x_out);
     }
+    fill<int32_t>(w.queues, 0, kQueueInts, s);
+    const unsigned sweep_grid = grid;
     for (int it = 0; it < stress_iters; ++it) {
         float2* out = bufs[next];
-        hipLaunchKernelGGL((batch_layout_kernel<kLayoutStep>), dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off, G,
-                           w.plan.rb_pre, w.plan.rb_graph, w.inv, cur, out, w.wsum, nullptr);
+        int32_t* qc = w.queues + (it % 2) * kXcdQueues * kQueueStride;
+        int32_t* qn = w.queues + ((it + 1) % 2) * kXcdQueues * kQueueStride;
+        hipLaunchKernelGGL(batch_sweep_kernel, dim3(sweep_grid), dim3(256), 0, s, b->node_off, b->mat_off, G,
+                           w.plan.rb_pre, w.plan.rl_graph, w.plan.rl_start, w.inv, cur, out, w.wsum, qc, qn);
         cur = out;
         next ^= 1;
     }
     if (stress_out) {
         hipLaunchKernelGGL((batch_layout_kernel<kLayoutStress>), dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off,
-                           G, w.plan.rb_pre, w.plan.rb_graph, w.inv, cur, nullptr, nullptr, w.part);
+                           G, w.plan.rb_pre, w.plan.rb_graph, w.plan.rb_pre, w.inv, cur, nullptr, nullptr, w.part);
         hipLaunchKernelGGL(batch_stress_sum_kernel, dim3((G + 255) / 256), dim3(256), 0, s, w.plan.rb_pre, G, w.part,
                            stress_out);
     }

@@ -34,9 +34,11 @@ enum {
     kLayoutWsum = 5,        // per-row sum_j Delta_ij^-2 (the diagonal of L^w)
 };
 
-// Squared distances are floored here before the reciprocal square root, so
-// that a coincident pair (and the diagonal) gets a finite 1/d; its direction
-// term c * (X_i - X_j) is then exactly zero because X_i - X_j is.
+// Added to every squared distance before the reciprocal square root, so that
+// a coincident pair (and the diagonal) gets a finite 1/d; its direction term
+// c * (X_i - X_j) is then exactly zero because X_i - X_j is.  For squared
+// distances above ~2e-23 the term is below half an ulp and changes nothing
+// beyond the rounding of the sum itself.
 constexpr float kMinSq = 1e-30f;
 
 constexpr int kLayoutRowsPerWave = 4;
@@ -58,8 +60,8 @@ __device__ __forceinline__ void layout_pair(float Dv, bool off, float2 xi, float
     if (WSUM) return;
     const float dx = xi.x - xj.x;
     const float dy = xi.y - xj.y;
-    const float r2 = fmaf(dx, dx, dy * dy);
-    const float rs = __builtin_amdgcn_rsqf(fmaxf(r2, kMinSq));
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, kMinSq));
+    const float rs = __builtin_amdgcn_rsqf(r2);
     if (STEP) {
         const float c = inv * rs;
         ax = fmaf(w, xj.x, fmaf(c, dx, ax));
