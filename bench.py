@@ -164,14 +164,18 @@ def spmm_stream(ops, dev, n=20000, gamma=2.5, avg_degree=20, tol=1e-7, reps=2):
                 work=f"{alg:.4g} B over {T - 1} pushes", nnz=nnz)
 
 
-def counters_pass(ops, b, x0):
-    """One eager batched pass, then a plain 1 GiB device copy, for rocprofv3
-    --pmc runs: the copy's FETCH_SIZE / WRITE_SIZE calibrate the counters."""
+def counters_pass(ops, b, x0, dev):
+    """One eager batched pass, one streaming SpMM run, then a plain 1 GiB
+    device copy, for rocprofv3 --pmc runs: the copy's FETCH_SIZE / WRITE_SIZE
+    calibrate the counters."""
     import torch
 
     bufs = b.buffers(x0)
     ms = ops.pprviz_batch_profile(b, bufs, alpha=ALPHA, tol=TOL, stress_iters=STRESS_ITERS)
     log(f"eager pass stage ms {ms}")
+    del bufs
+    sp = spmm_stream(ops, dev, reps=1)
+    log(f"streaming SpMM {sp['ms']:.1f} ms")
     a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     c = torch.empty_like(a)
     torch.cuda.synchronize()
@@ -218,7 +222,7 @@ def main():
     bufs = b.buffers(x0)
     T, _ = ops.pushes_for_tolerance(ALPHA, TOL, 100000)
     if args.counters:
-        counters_pass(ops, b, x0)
+        counters_pass(ops, b, x0, dev)
         return
     plan = ops.BatchPlan(b, bufs, alpha=ALPHA, tol=TOL, stress_iters=STRESS_ITERS)
     stream = torch.cuda.current_stream()
