@@ -160,7 +160,8 @@ ppr_status stress_eval(const float* delta, int32_t k, const float* x, double* st
  * term (L^Y is zero there).  Same fixed points as the exact update
  * X = (L^w)^-1 L^Y Y; O(k^2) per step, no linear solve.
  * x_out must not alias x_in.  stress_out: DEVICE double[1] or NULL, receives
- * L(x_in | Delta).
+ * L(x_in | Delta).  One launch per step: the row sweep of this entry point
+ * reads Delta[i][:] for each row i, so delta need not be symmetric here.
  */
 ppr_status layout_step(const float* delta, int32_t k, const float* x_in, float* x_out,
                        double* stress_out, void* ws, size_t ws_bytes, void* stream);

@@ -11,10 +11,10 @@
 //            (subgraph, source tile) tasks from an atomic counter in LPT order
 //            and run the LDS-resident power iteration of ppr_core.hpp.
 //  pdist     grid-stride over (subgraph, 64x64 tile) items.
-//  layout    the row sums of Delta^-2 (one pass), then stress_iters sweep
-//            launches that pop (subgraph, 16-row block) items, largest
-//            subgraphs first, from per-XCD queues; then one stress pass of
-//            the final layout.
+//  layout    per-node sums of Delta^-2 (one pair-tile pass), then
+//            stress_iters sweeps, each a pair-tile pass over the 64x64 tiles
+//            of one triangle of every subgraph plus a pass that combines the
+//            partial blocks; then one stress pass of the final layout.
 #include <math.h>
 
 #include <algorithm>
@@ -27,7 +27,6 @@ namespace pprviz {
 
 constexpr int kBatchMaxN = Res<16>::NMAX;  // 2304
 constexpr int kPlanThreads = 1024;
-constexpr int kXcdQueues = 8;
 
 struct BatchPlan {
     int32_t* order;      // [G] subgraph ids, largest first
@@ -36,9 +35,11 @@ struct BatchPlan {
     int64_t* rb_pre;     // [G+1] prefix of 16-row layout blocks (subgraph order)
     int32_t* pd_graph;   // subgraph of each PDist tile item
     int32_t* rb_graph;   // subgraph of each layout row-block item
-    int64_t* rl_pre;     // [G+1] prefix of 16-row layout blocks in LPT order
-    int64_t* rl_start;   // [G] first LPT item of each subgraph
-    int32_t* rl_graph;   // subgraph of each layout row-block item in LPT order
+    int64_t* pt_pre;     // [G+1] prefix of 64x64 pair tiles (I <= J) of the layout sweeps
+    int32_t* pt_graph;   // subgraph of each pair tile
+    int64_t* rt_pre;     // [G+1] prefix of 64-row tiles (sweep finalize items)
+    int32_t* rt_graph;   // subgraph of each 64-row tile
+    int64_t* pb_pre;     // [G+1] prefix of the partial blocks, T*T*64 floats per subgraph
     int32_t* counter;    // [3] PPR task queue heads, one per tile width
     int32_t* cls_pos;    // [4] first LPT position of the 16-, 32- and 64-column classes, then G
 };
@@ -62,6 +63,32 @@ __device__ __forceinline__ int find_segment(const int64_t* __restrict__ pre, int
 __device__ __forceinline__ int64_t tiles_of(int n) {
     const int cols = res_cols_for(n);
     return cols == 0 ? 0 : (n + cols - 1) / cols;
+}
+
+constexpr int kPlanPrefixes = 6;
+
+__device__ __forceinline__ int64_t* plan_prefix(const BatchPlan& p, int which) {
+    switch (which) {
+        case 0: return p.tile_pre;
+        case 1: return p.pd_pre;
+        case 2: return p.rb_pre;
+        case 3: return p.pt_pre;
+        case 4: return p.rt_pre;
+        default: return p.pb_pre;
+    }
+}
+
+// Items of an n-node subgraph for each prefix of the plan.
+__device__ __forceinline__ int64_t plan_count(int which, int n) {
+    const int64_t T = (n + kPT - 1) / kPT;
+    switch (which) {
+        case 0: return tiles_of(n);                                          // PPR source tiles
+        case 1: return T * T;                                                // PDist 64x64 tiles
+        case 2: return (n + kLayoutRowsPerBlock - 1) / kLayoutRowsPerBlock;  // stress row blocks
+        case 3: return T * (T + 1) / 2;                                      // pair tiles I <= J
+        case 4: return T;                                                    // 64-row tiles
+        default: return T * T * kPT;                                         // partial-block floats
+    }
 }
 
 __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t* __restrict__ node_off, int32_t G,
@@ -89,20 +116,15 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t*
     }
     __syncthreads();
     __threadfence_block();
-    // four prefix sums (sequential chunks per thread, then a block scan):
-    // PPR tiles in LPT order, PDist tiles and layout row blocks in subgraph
-    // order, layout row blocks in LPT order
-    for (int which = 0; which < 4; ++which) {
-        int64_t* out = which == 0 ? p.tile_pre : (which == 1 ? p.pd_pre : (which == 2 ? p.rb_pre : p.rl_pre));
+    // prefix sums (sequential chunks per thread, then a block scan): PPR
+    // tiles in LPT order; PDist tiles, stress row blocks, layout pair tiles,
+    // 64-row tiles and partial-block floats in subgraph order
+    for (int which = 0; which < kPlanPrefixes; ++which) {
+        int64_t* out = plan_prefix(p, which);
         const int per = (G + kPlanThreads - 1) / kPlanThreads;
         const int a = tid * per, b = min(G, a + per);
         int64_t loc = 0;
-        for (int i = a; i < b; ++i) {
-            const int g = (which == 0 || which == 3) ? p.order[i] : i;
-            const int n = graph_n(node_off, g);
-            loc += which == 0 ? tiles_of(n) : (which == 1 ? (int64_t)((n + 63) / 64) * ((n + 63) / 64)
-                                                          : (int64_t)((n + kLayoutRowsPerBlock - 1) / kLayoutRowsPerBlock));
-        }
+        for (int i = a; i < b; ++i) loc += plan_count(which, graph_n(node_off, which == 0 ? p.order[i] : i));
         scan_tmp[tid] = loc;
         __syncthreads();
         if (tid == 0) {
@@ -117,10 +139,7 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t*
         int64_t run = scan_tmp[tid];
         for (int i = a; i < b; ++i) {
             out[i] = run;
-            const int g = (which == 0 || which == 3) ? p.order[i] : i;
-            const int n = graph_n(node_off, g);
-            run += which == 0 ? tiles_of(n) : (which == 1 ? (int64_t)((n + 63) / 64) * ((n + 63) / 64)
-                                                          : (int64_t)((n + kLayoutRowsPerBlock - 1) / kLayoutRowsPerBlock));
+            run += plan_count(which, graph_n(node_off, which == 0 ? p.order[i] : i));
         }
         if (tid == kPlanThreads - 1) out[G] = run;
         __syncthreads();
@@ -130,10 +149,9 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t*
         for (int64_t i = p.pd_pre[g]; i < p.pd_pre[g + 1]; ++i) p.pd_graph[i] = g;
         for (int64_t i = p.rb_pre[g]; i < p.rb_pre[g + 1]; ++i) p.rb_graph[i] = g;
     }
-    for (int pos = tid; pos < G; pos += kPlanThreads) {
-        const int g = p.order[pos];
-        p.rl_start[g] = p.rl_pre[pos];
-        for (int64_t i = p.rl_pre[pos]; i < p.rl_pre[pos + 1]; ++i) p.rl_graph[i] = g;
+    for (int g = tid; g < G; g += kPlanThreads) {
+        for (int64_t i = p.pt_pre[g]; i < p.pt_pre[g + 1]; ++i) p.pt_graph[i] = g;
+        for (int64_t i = p.rt_pre[g]; i < p.rt_pre[g + 1]; ++i) p.rt_graph[i] = g;
     }
     // Sizes are sorted descending, so each tile width owns a contiguous range
     // of positions: n > Res<32>::NMAX (16 columns), then n > Res<64>::NMAX
@@ -236,27 +254,25 @@ __global__ __launch_bounds__(256) void batch_pdist_kernel(const int64_t* __restr
     }
 }
 
-// Layout row blocks of every subgraph, grid-stride over (subgraph, 16 rows)
-// items.  item_graph / graph_start give each item's subgraph and the first
-// item of that subgraph: subgraph order (rb_graph, rb_pre) where the item
-// index also names a stress partial, largest subgraphs first (rl_graph,
-// rl_start) for the sweeps, so that the blocks' shares come out even.
+// Row kernels over (subgraph, 16 rows) items, grid-stride: pre is the
+// per-subgraph prefix of the item list and item_graph its subgraph map.
+// Used for the stress of the final layout, whose per-item partials are then
+// summed per subgraph in item order.
 template <int MODE>
 __global__ __launch_bounds__(256) void batch_layout_kernel(const int64_t* __restrict__ node_off,
                                                            const int64_t* __restrict__ mat_off, int32_t G,
-                                                           const int64_t* __restrict__ rb_pre,
+                                                           const int64_t* __restrict__ pre,
                                                            const int32_t* __restrict__ item_graph,
-                                                           const int64_t* __restrict__ graph_start,
                                                            const float* __restrict__ inv,
                                                            const float2* __restrict__ x, float2* __restrict__ xout,
                                                            float* __restrict__ wsum, double* __restrict__ part) {
     __shared__ double red[4];
     const int wave = threadIdx.x >> 6;
-    const int64_t total = rb_pre[G];
+    const int64_t total = pre[G];
     for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
         const int g = item_graph[item];
         const int k = graph_n(node_off, g);
-        const int64_t rb = item - graph_start[g];
+        const int64_t rb = item - pre[g];
         const int64_t nb = node_off[g];
         const int row_begin = (int)(rb * kLayoutRowsPerBlock) + wave * kLayoutRowsPerWave;
         const double st = layout_rows<MODE, true>(inv + mat_off[g], k, k, x + nb, row_begin,
@@ -271,46 +287,60 @@ __global__ __launch_bounds__(256) void batch_layout_kernel(const int64_t* __rest
     }
 }
 
-// Queue heads of one sweep: one per XCD, each on its own 128-byte line.
-constexpr int kQueueStride = 32;
-constexpr int kQueueInts = 2 * kXcdQueues * kQueueStride;  // two sweeps' worth
-
-// One Jacobi sweep over all subgraphs with dynamic scheduling.  Items (16
-// rows of one subgraph) are in LPT order and dealt round-robin into 8 queues;
-// a block drains the queue of its own XCD (blocks go to XCDs round-robin by
-// id) and then helps with the others.  Which block takes an item does not
-// change any result.  The launch also clears the heads the next sweep will
-// use (q_next), which the previous sweep finished with.
-__global__ __launch_bounds__(256) void batch_sweep_kernel(const int64_t* __restrict__ node_off,
-                                                          const int64_t* __restrict__ mat_off, int32_t G,
-                                                          const int64_t* __restrict__ rb_pre,
-                                                          const int32_t* __restrict__ rl_graph,
-                                                          const int64_t* __restrict__ rl_start,
-                                                          const float* __restrict__ inv,
-                                                          const float2* __restrict__ x, float2* __restrict__ xout,
-                                                          float* __restrict__ wsum, int32_t* __restrict__ q_cur,
-                                                          int32_t* __restrict__ q_next) {
-    __shared__ int64_t s_item;
+// Pair-tile pass over every subgraph (see pair_tile): wave w of the grid
+// takes tiles w, w + W, w + 2W, ... (W waves in all); tiles cost about the
+// same, so the static deal is even.
+template <int MODE>
+__global__ __launch_bounds__(256) void batch_pair_kernel(const int64_t* __restrict__ node_off,
+                                                         const int64_t* __restrict__ mat_off, int32_t G,
+                                                         const int64_t* __restrict__ pt_pre,
+                                                         const int32_t* __restrict__ pt_graph,
+                                                         const int64_t* __restrict__ pb_pre,
+                                                         const float* __restrict__ inv,
+                                                         const float2* __restrict__ x, float* __restrict__ px,
+                                                         float* __restrict__ py, float* __restrict__ pw) {
+    __shared__ PairLdsOf<MODE> lds[4];
     const int wave = threadIdx.x >> 6;
-    if (blockIdx.x == 0 && threadIdx.x < kXcdQueues) q_next[threadIdx.x * kQueueStride] = 0;
-    const int64_t total = rb_pre[G];
-    const int home = blockIdx.x % kXcdQueues;
-    for (int t = 0; t < kXcdQueues; ++t) {
-        const int qid = (home + t) % kXcdQueues;
-        for (;;) {
-            if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(&q_cur[qid * kQueueStride], 1) * kXcdQueues + qid;
-            __syncthreads();
-            const int64_t item = s_item;
-            __syncthreads();
-            if (item >= total) break;
-            const int g = rl_graph[item];
-            const int k = graph_n(node_off, g);
-            const int64_t rb = item - rl_start[g];
-            const int64_t nb = node_off[g];
-            const int row_begin = (int)(rb * kLayoutRowsPerBlock) + wave * kLayoutRowsPerWave;
-            layout_rows<kLayoutStep, true>(inv + mat_off[g], k, k, x + nb, row_begin, xout + nb, 1.f, nullptr,
-                                           nullptr, wsum + nb);
-        }
+    const int64_t total = pt_pre[G];
+    const int64_t W = (int64_t)gridDim.x * 4;
+    for (int64_t item = (int64_t)blockIdx.x * 4 + wave; item < total; item += W) {
+        const int64_t it = __builtin_amdgcn_readfirstlane((int)item);
+        const int g = __builtin_amdgcn_readfirstlane(pt_graph[it]);
+        const int k = graph_n(node_off, g);
+        const int T = (k + kPT - 1) / kPT;
+        int I, J;
+        pair_tile_ij((int)(it - pt_pre[g]), I, J);
+        const int64_t pb = pb_pre[g];
+        pair_tile<true, MODE>(inv + mat_off[g], k, k, x + node_off[g], I, J, T, px + pb, py + pb, pw + pb,
+                              lds[wave]);
+    }
+}
+
+// Combine the partial blocks: one wave per 64-row tile of a subgraph.
+template <int MODE>
+__global__ __launch_bounds__(256) void batch_pair_finalize_kernel(const int64_t* __restrict__ node_off, int32_t G,
+                                                                  const int64_t* __restrict__ rt_pre,
+                                                                  const int32_t* __restrict__ rt_graph,
+                                                                  const int64_t* __restrict__ pb_pre,
+                                                                  const float* __restrict__ px,
+                                                                  const float* __restrict__ py,
+                                                                  const float* __restrict__ pw,
+                                                                  const float2* __restrict__ x,
+                                                                  float2* __restrict__ xout,
+                                                                  float* __restrict__ wsum) {
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t total = rt_pre[G];
+    for (int64_t item = (int64_t)blockIdx.x * 4 + wave; item < total; item += (int64_t)gridDim.x * 4) {
+        const int g = rt_graph[item];
+        const int k = graph_n(node_off, g);
+        const int T = (k + kPT - 1) / kPT;
+        const int i = (int)(item - rt_pre[g]) * kPT + lane;
+        if (i >= k) continue;
+        const int64_t nb = node_off[g];
+        const int64_t pb = pb_pre[g];
+        pair_finalize<MODE>(i, T, px + pb, py + pb, pw + pb, x + nb, xout ? xout + nb : nullptr,
+                            wsum ? wsum + nb : nullptr);
     }
 }
 
@@ -338,7 +368,9 @@ struct BatchWs {
     float* wsum;  // per node sum_j Delta^-2
     float* xtmp;
     double* part;
-    int32_t* queues;  // sweep queue heads, two sweeps' worth
+    float* px;  // pair-tile partial blocks of the sweeps (x, y, weight)
+    float* py;
+    float* pw;
     BatchPlan plan;
 };
 
@@ -353,7 +385,11 @@ static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     t.xtmp = c.template take<float>((size_t)b->n_nodes * 2);
     // row blocks: sum over g of ceil(n_g/16) <= n_nodes/16 + G
     t.part = c.template take<double>((size_t)(b->n_nodes / kLayoutRowsPerBlock + b->n_graphs + 1));
-    t.queues = c.template take<int32_t>(kQueueInts);
+    // partial blocks: sum_g ceil(n_g/64)^2 * 64 <= (pool/4096 + n_nodes/32 + G) * 64 floats
+    const size_t pblk = (size_t)(b->pool_size / 4096 + b->n_nodes / 32 + b->n_graphs + 1) * kPT;
+    t.px = c.template take<float>(pblk);
+    t.py = c.template take<float>(pblk);
+    t.pw = c.template take<float>(pblk);
     t.plan.order = c.template take<int32_t>((size_t)b->n_graphs);
     t.plan.tile_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
     t.plan.pd_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
@@ -362,9 +398,13 @@ static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     // sum_g ceil(n_g/16) <= n_nodes/16 + G
     t.plan.pd_graph = c.template take<int32_t>((size_t)(b->pool_size / 4096 + b->n_nodes / 32 + b->n_graphs + 1));
     t.plan.rb_graph = c.template take<int32_t>((size_t)(b->n_nodes / kLayoutRowsPerBlock + b->n_graphs + 1));
-    t.plan.rl_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
-    t.plan.rl_start = c.template take<int64_t>((size_t)b->n_graphs);
-    t.plan.rl_graph = c.template take<int32_t>((size_t)(b->n_nodes / kLayoutRowsPerBlock + b->n_graphs + 1));
+    // pair tiles: sum_g T(T+1)/2 <= pool/8192 + 3 n_nodes/128 + G; 64-row tiles <= n_nodes/64 + G
+    t.plan.pt_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
+    t.plan.pt_graph = c.template take<int32_t>((size_t)(b->pool_size / 8192 + 3 * b->n_nodes / 128 + b->n_graphs + 1));
+    t.plan.rt_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
+    t.plan.rt_graph = c.template take<int32_t>((size_t)(b->n_nodes / kPT + b->n_graphs + 1));
+    t.plan.pb_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
+
     t.plan.counter = c.template take<int32_t>(64);
     t.plan.cls_pos = c.template take<int32_t>(64);
     if (w) *w = t;
@@ -375,6 +415,19 @@ static int device_cu_count() {
     if (hipGetDevice(&dev) != hipSuccess) return 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
     return cus;
+}
+
+// Blocks of the pair-tile kernel that one CU holds at once (the static tile
+// deal assumes every block of the grid is resident).
+template <int MODE>
+static int pair_blocks_per_cu() {
+    static const int nb = [] {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, batch_pair_kernel<MODE>, 256, 0) != hipSuccess || v < 1)
+            v = 4;
+        return v;
+    }();
+    return nb;
 }
 
 static ppr_status batch_validate(const ppr_batch* b, float alpha, int32_t max_iter, int32_t stress_iters,
@@ -425,14 +478,19 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     hipLaunchKernelGGL((batch_ppr_kernel<64, 2>), dim3(cus), dim3(kResThreads), 0, s, ba, w.plan);
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[2], s));
 
-    // 8 blocks of 4 waves per CU: every block resident at once
     const unsigned grid = (unsigned)cus * 8;
     hipLaunchKernelGGL(batch_pdist_kernel, dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off, G, w.plan.pd_pre,
                        w.plan.pd_graph, dppr_pool, delta_pool, w.inv);
-    hipLaunchKernelGGL((batch_layout_kernel<kLayoutWsum>), dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off, G,
-                       w.plan.rb_pre, w.plan.rb_graph, w.plan.rb_pre, w.inv, reinterpret_cast<const float2*>(x0),
-                       nullptr, w.wsum,
-                       nullptr);
+    const unsigned pgrid = (unsigned)cus * pair_blocks_per_cu<kPairStep>();
+    const unsigned wgrid = (unsigned)cus * pair_blocks_per_cu<kPairW>();
+    const unsigned fgrid = (unsigned)cus * 8;
+    // per-node weight sums, from the pair tiles in the order the sweeps use
+    hipLaunchKernelGGL((batch_pair_kernel<kPairW>), dim3(wgrid), dim3(256), 0, s, b->node_off, b->mat_off, G,
+                       w.plan.pt_pre, w.plan.pt_graph, w.plan.pb_pre, w.inv, reinterpret_cast<const float2*>(x0),
+                       w.px, w.py, w.pw);
+    hipLaunchKernelGGL((batch_pair_finalize_kernel<kPairW>), dim3(fgrid), dim3(256), 0, s, b->node_off, G,
+                       w.plan.rt_pre, w.plan.rt_graph, w.plan.pb_pre, w.px, w.py, w.pw,
+                       reinterpret_cast<const float2*>(x0), nullptr, w.wsum);
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[3], s));
 
     // Jacobi sweeps, ping-pong so that the last one lands in x_out.
@@ -443,20 +501,18 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
         hipLaunchKernelGGL(copy_kernel, dim3(1024), dim3(256), 0, s, x0, x_out, b->n_nodes * 2);
         cur = reinterpret_cast<const float2*>(x_out);
     }
-    fill<int32_t>(w.queues, 0, kQueueInts, s);
-    const unsigned sweep_grid = grid;
     for (int it = 0; it < stress_iters; ++it) {
         float2* out = bufs[next];
-        int32_t* qc = w.queues + (it % 2) * kXcdQueues * kQueueStride;
-        int32_t* qn = w.queues + ((it + 1) % 2) * kXcdQueues * kQueueStride;
-        hipLaunchKernelGGL(batch_sweep_kernel, dim3(sweep_grid), dim3(256), 0, s, b->node_off, b->mat_off, G,
-                           w.plan.rb_pre, w.plan.rl_graph, w.plan.rl_start, w.inv, cur, out, w.wsum, qc, qn);
+        hipLaunchKernelGGL((batch_pair_kernel<kPairStep>), dim3(pgrid), dim3(256), 0, s, b->node_off, b->mat_off,
+                           G, w.plan.pt_pre, w.plan.pt_graph, w.plan.pb_pre, w.inv, cur, w.px, w.py, w.pw);
+        hipLaunchKernelGGL((batch_pair_finalize_kernel<kPairStep>), dim3(fgrid), dim3(256), 0, s, b->node_off, G,
+                           w.plan.rt_pre, w.plan.rt_graph, w.plan.pb_pre, w.px, w.py, w.pw, cur, out, w.wsum);
         cur = out;
         next ^= 1;
     }
     if (stress_out) {
         hipLaunchKernelGGL((batch_layout_kernel<kLayoutStress>), dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off,
-                           G, w.plan.rb_pre, w.plan.rb_graph, w.plan.rb_pre, w.inv, cur, nullptr, nullptr, w.part);
+                           G, w.plan.rb_pre, w.plan.rb_graph, w.inv, cur, nullptr, nullptr, w.part);
         hipLaunchKernelGGL(batch_stress_sum_kernel, dim3((G + 255) / 256), dim3(256), 0, s, w.plan.rb_pre, G, w.part,
                            stress_out);
     }

@@ -193,6 +193,256 @@ __global__ __launch_bounds__(256) void layout_rows_kernel(const float* __restric
     }
 }
 
+// ---------------------------------------------------------------------------
+// Pair-tile Jacobi sweep.  Delta is symmetric, so each unordered pair {i, j}
+// is evaluated once and feeds both rows: with d = X_i - X_j,
+//     row i gets   w X_j + c d        row j gets   w X_i - c d
+// (the two terms of the sweep formula in layout_rows, seen from each end).
+// The k x k matrix is cut into 64 x 64 tiles (I, J), I <= J.  One wave takes
+// one tile: lane l is row i = 64 I + l, and the wave walks the 64 columns j
+// of tile J one per step, reading Delta[j][i] (row j, so the 64 lanes read
+// 256 contiguous bytes).  Row sums stay in the lane; the column sums of 8
+// steps at a time go through a small LDS block, where 8 lanes per column add
+// 8 rows each and three lane exchanges finish the column.  A diagonal tile
+// (I == J) takes every ordered pair and feeds rows only.
+//
+// Each tile writes its sums to a partial block: P[I][J] holds what the rows
+// of tile I received from the columns of tile J (and P[J][I] the reverse), so
+// a node's total is the sum of its T blocks in block order, independent of
+// which wave ran which tile.  pair_finalize combines them.
+//
+// Memory read per sweep: the tiles of one triangle (about half of Delta).
+constexpr int kPT = 64;
+constexpr int kPTChunk = 8;
+
+// LDS of one wave for the column sums of one chunk, per row and column:
+// (x, y) when positions are summed, w when weights are.
+template <bool POS, bool WGT>
+struct PairLds;
+template <>
+struct PairLds<true, false> {
+    float2 xy[kPTChunk][kWave];
+};
+template <>
+struct PairLds<true, true> {
+    float2 xy[kPTChunk][kWave];
+    float w[kPTChunk][kWave];
+};
+template <>
+struct PairLds<false, true> {
+    float w[kPTChunk][kWave];
+};
+
+enum { kPairStep = 0, kPairStepW = 1, kPairW = 2 };
+
+// Upper-triangle tile index t -> (I, J), I <= J, row-major over J: t = J (J + 1) / 2 + I.
+__device__ __forceinline__ void pair_tile_ij(int t, int& I, int& J) {
+    int j = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((j + 1) * (j + 2) / 2 <= t) ++j;
+    while (j * (j + 1) / 2 > t) --j;
+    J = j;
+    I = t - j * (j + 1) / 2;
+}
+
+// Per-tile state of one wave in pair_tile_body.
+struct PairTileCtx {
+    int lane, i, j0, ncol, I, J, T, cc, cp;
+    bool row_ok;
+    float2 xi;
+};
+
+// Loads of one 8-column chunk: m[j][i] for the lane's row and the chunk's
+// columns (one coalesced 256-byte row segment per column), and X_j.
+template <bool POS, bool FULL>
+__device__ __forceinline__ void pair_load(const PairTileCtx& t, const float* __restrict__ mcol, int64_t ld,
+                                          int32_t k, const float2* __restrict__ x, int q, float (&mv)[kPTChunk],
+                                          float2 (&xj)[kPTChunk]) {
+    const int jq = t.j0 + q * kPTChunk;
+#pragma unroll
+    for (int s = 0; s < kPTChunk; ++s) {
+        const bool col_ok = FULL || (q * kPTChunk + s < t.ncol);
+        mv[s] = (col_ok && t.row_ok) ? mcol[(int64_t)(jq + s) * ld] : 0.f;
+        if (POS) xj[s] = x[FULL ? jq + s : min(jq + s, k - 1)];
+    }
+}
+
+// Arithmetic of one chunk: row sums into (ax, ay, aw); for an off-diagonal
+// tile the column terms go through LDS and each column's sum over the 64
+// rows is written to the partial block P[J][I].
+template <bool INV, int MODE, bool DIAG, bool FULL, typename Lds>
+__device__ __forceinline__ void pair_chunk(const PairTileCtx& t, int q, const float (&mv)[kPTChunk],
+                                           const float2 (&xj)[kPTChunk], float& ax, float& ay, float& aw,
+                                           float* __restrict__ px, float* __restrict__ py, float* __restrict__ pw,
+                                           Lds& L) {
+    constexpr bool POS = (MODE != kPairW);
+    constexpr bool WGT = (MODE != kPairStep);
+    const int jq = t.j0 + q * kPTChunk;
+#pragma unroll
+    for (int s = 0; s < kPTChunk; ++s) {
+        const int j = jq + s;
+        float inv;
+        if (INV) {
+            inv = mv[s];
+        } else {
+            const bool col_ok = FULL || (q * kPTChunk + s < t.ncol);
+            inv = (col_ok && t.row_ok && (!DIAG || j != t.i)) ? __builtin_amdgcn_rcpf(mv[s]) : 0.f;
+        }
+        const float w = inv * inv;
+        float cx = 0.f, cy = 0.f;
+        if (POS) {
+            const float dx = t.xi.x - xj[s].x;
+            const float dy = t.xi.y - xj[s].y;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, kMinSq));
+            const float c = inv * __builtin_amdgcn_rsqf(r2);
+            const float tx = c * dx;
+            const float ty = c * dy;
+            ax = fmaf(w, xj[s].x, ax) + tx;
+            ay = fmaf(w, xj[s].y, ay) + ty;
+            cx = fmaf(w, t.xi.x, -tx);
+            cy = fmaf(w, t.xi.y, -ty);
+        }
+        if (WGT) aw += w;
+        if (!DIAG) {
+            if constexpr (POS) L.xy[s][t.lane] = make_float2(cx, cy);
+            if constexpr (WGT) L.w[s][t.lane] = w;
+        }
+    }
+    if (DIAG) return;
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    float sx = 0.f, sy = 0.f, sw = 0.f;
+    // lane (cc, cp) adds rows cp*8 .. cp*8+7 of column cc, starting at row
+    // cp*8 + cp so that the 8 lanes of a column read 8 different bank groups
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int r = t.cp * 8 + ((u + t.cp) & 7);
+        if constexpr (POS) {
+            const float2 v = L.xy[t.cc][r];
+            sx += v.x;
+            sy += v.y;
+        }
+        if constexpr (WGT) sw += L.w[t.cc][r];
+    }
+    if (POS) {
+        sx += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sx), 0xB1, 0xf, 0xf, false));
+        sy += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sy), 0xB1, 0xf, 0xf, false));
+        sx += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sx), 0x4E, 0xf, 0xf, false));
+        sy += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sy), 0x4E, 0xf, 0xf, false));
+        sx += __shfl_xor(sx, 4, kWave);
+        sy += __shfl_xor(sy, 4, kWave);
+    }
+    if (WGT) {
+        sw += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sw), 0xB1, 0xf, 0xf, false));
+        sw += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sw), 0x4E, 0xf, 0xf, false));
+        sw += __shfl_xor(sw, 4, kWave);
+    }
+    const int jj = q * kPTChunk + t.cc;
+    if (t.cp == 0 && (FULL || jj < t.ncol)) {
+        const int64_t o = ((int64_t)t.J * t.T + t.I) * kPT + jj;
+        if (POS) {
+            px[o] = sx;
+            py[o] = sy;
+        }
+        if (WGT) pw[o] = sw;
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// One 64 x 64 tile.  MODE kPairStep: position sums only (the weight sums come
+// from a kPairW pass); kPairStepW: positions and weights; kPairW: weights
+// only.  INV: `m` holds 1/Delta with a zero diagonal, else Delta.  px, py, pw
+// are this subgraph's partial blocks ([T][T][64]).  DIAG: I == J.  FULL: all
+// 64 columns of tile J exist (no column bound checks).  The loads of the next
+// chunk are issued before the arithmetic of the current one (two register
+// sets, used alternately).
+template <bool INV, int MODE, bool DIAG, bool FULL, typename Lds>
+__device__ __forceinline__ void pair_tile_body(const float* __restrict__ m, int64_t ld, int32_t k,
+                                               const float2* __restrict__ x, int I, int J, int T,
+                                               float* __restrict__ px, float* __restrict__ py,
+                                               float* __restrict__ pw, Lds& L) {
+    constexpr bool POS = (MODE != kPairW);
+    PairTileCtx t;
+    t.lane = threadIdx.x & 63;
+    t.i = I * kPT + t.lane;
+    t.row_ok = t.i < k;
+    t.xi = t.row_ok ? x[t.i] : make_float2(0.f, 0.f);
+    t.j0 = J * kPT;
+    t.ncol = FULL ? kPT : min(kPT, k - t.j0);
+    t.I = I;
+    t.J = J;
+    t.T = T;
+    t.cc = t.lane >> 3;
+    t.cp = t.lane & 7;
+    const float* __restrict__ mcol = m + t.i;
+    const int nq = (t.ncol + kPTChunk - 1) / kPTChunk;
+    float ax = 0.f, ay = 0.f, aw = 0.f;
+    float ma[kPTChunk], mb[kPTChunk];
+    float2 xa[kPTChunk], xb[kPTChunk];
+    pair_load<POS, FULL>(t, mcol, ld, k, x, 0, ma, xa);
+    for (int q = 0; q < nq; q += 2) {
+        if (q + 1 < nq) pair_load<POS, FULL>(t, mcol, ld, k, x, q + 1, mb, xb);
+        pair_chunk<INV, MODE, DIAG, FULL>(t, q, ma, xa, ax, ay, aw, px, py, pw, L);
+        if (q + 1 < nq) {
+            if (q + 2 < nq) pair_load<POS, FULL>(t, mcol, ld, k, x, q + 2, ma, xa);
+            pair_chunk<INV, MODE, DIAG, FULL>(t, q + 1, mb, xb, ax, ay, aw, px, py, pw, L);
+        }
+    }
+    if (t.row_ok) {
+        const int64_t o = ((int64_t)I * T + J) * kPT + t.lane;
+        if (POS) {
+            px[o] = ax;
+            py[o] = ay;
+        }
+        if (MODE != kPairStep) pw[o] = aw;
+    }
+}
+
+// LDS type of a pair-tile launch in mode MODE.
+template <int MODE>
+using PairLdsOf = PairLds<MODE != kPairW, MODE != kPairStep>;
+
+template <bool INV, int MODE>
+__device__ __forceinline__ void pair_tile(const float* __restrict__ m, int64_t ld, int32_t k,
+                                          const float2* __restrict__ x, int I, int J, int T,
+                                          float* __restrict__ px, float* __restrict__ py,
+                                          float* __restrict__ pw, PairLdsOf<MODE>& L) {
+    const bool full = (J + 1) * kPT <= k;
+    if (I == J) {
+        pair_tile_body<INV, MODE, true, false>(m, ld, k, x, I, J, T, px, py, pw, L);
+    } else if (full) {
+        pair_tile_body<INV, MODE, false, true>(m, ld, k, x, I, J, T, px, py, pw, L);
+    } else {
+        pair_tile_body<INV, MODE, false, false>(m, ld, k, x, I, J, T, px, py, pw, L);
+    }
+}
+
+// Node i of a k-node subgraph: combine its T partial blocks in block order.
+// MODE kPairW writes the weight sum; the step modes write X+_i (or X_i when
+// the weight sum is zero), taking the weight sum from `wsum` (kPairStep) or
+// from the partials (kPairStepW).
+template <int MODE>
+__device__ __forceinline__ void pair_finalize(int i, int T, const float* __restrict__ px,
+                                              const float* __restrict__ py, const float* __restrict__ pw,
+                                              const float2* __restrict__ x, float2* __restrict__ xout,
+                                              float* __restrict__ wsum) {
+    const int A = i / kPT, a = i % kPT;
+    const int64_t base = (int64_t)A * T * kPT + a;
+    float sx = 0.f, sy = 0.f, sw = 0.f;
+    for (int B = 0; B < T; ++B) {
+        const int64_t o = base + (int64_t)B * kPT;
+        if (MODE != kPairW) {
+            sx += px[o];
+            sy += py[o];
+        }
+        if (MODE != kPairStep) sw += pw[o];
+    }
+    if (MODE == kPairW) {
+        wsum[i] = sw;
+        return;
+    }
+    if (MODE == kPairStep) sw = wsum[i];
+    xout[i] = sw > 0.f ? make_float2(sx / sw, sy / sw) : x[i];
+}
+
 // out[0] = sum of part[0..m) in a fixed order (single block).
 static __global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ part, int64_t m,
                                                            double* __restrict__ out) {

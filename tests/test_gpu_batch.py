@@ -1,17 +1,30 @@
 """GPU parity of the batched path: many subgraphs in one enqueue / one HIP
-graph replay, against the plain one-subgraph-per-call path (same kernels, so
-the same bits) and against the FP64 oracle."""
+graph replay, against the plain one-subgraph-per-call path (PPR, DPPR and
+PDist run the same kernels, so the same bits; the batched layout sweep sums
+each unordered pair once over 64 x 64 tiles while the single-layout step
+sweeps rows, so the two layouts agree to rounding) and against the FP64
+oracle."""
 import numpy as np
 import pytest
 import torch
 
 import oracle as O
 import synth
-from gpu_util import ALPHA, PDIST_REL, get_ops, oracle_ppr, rel_err
+from gpu_util import ALPHA, PDIST_REL, STEP_REL, get_ops, oracle_ppr, rel_err
+
+# Batched vs single-layout trajectories after 50 sweeps: the same sums in
+# different FP32 orders, so the iterates drift apart by rounding that the
+# non-convex iteration can amplify; each single sweep is pinned to 1e-5 by
+# test_batch_one_sweep_matches_oracle.  Positions and final stress are
+# compared loosely here.
+LAYOUT_REL = 1e-2
+STRESS_TRAJ_REL = 1e-3
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [1, 2, 32, 45, 64, 100, 180, 300, 576, 577, 700, 1152, 1153, 1500, 2048, 2304]
+# tile-width boundaries of the PPR tile (576/577, 1152/1153) and of the row /
+# pair-tile layout sweeps (1024/1025)
+SIZES = [1, 2, 32, 45, 64, 100, 180, 300, 576, 577, 700, 1024, 1025, 1152, 1153, 1500, 2048, 2304]
 
 
 @pytest.fixture(scope="module")
@@ -32,6 +45,26 @@ def setup():
     return ops, gb, b, bufs, x0
 
 
+def test_batch_one_sweep_matches_oracle(setup):
+    # one batched sweep of every subgraph against the FP64 Jacobi step on the
+    # batch's own Delta (the per-step bar of the single-layout step)
+    ops, gb, b, bufs, x0 = setup
+    bufs1 = b.buffers(x0)
+    ops.pprviz_batch(b, bufs1, tol=1e-6, stress_iters=1)
+    torch.cuda.synchronize()
+    for gi, g in enumerate(gb.graphs):
+        n = g.n
+        a = int(gb.node_off[gi])
+        D = ops.graph_block(gb, bufs1["delta"], gi).double().cpu().numpy()
+        X = x0[a:a + n].double().cpu().numpy()
+        got = bufs1["x_out"][a:a + n].double().cpu().numpy()
+        if n == 1:
+            np.testing.assert_array_equal(got, X)
+            continue
+        want = O.jacobi_step(X, D)
+        assert np.abs(got - want).max() <= STEP_REL * np.abs(want).max(), (gi, n)
+
+
 def test_batch_equals_plain_path(setup):
     ops, gb, b, bufs, x0 = setup
     for gi, g in enumerate(gb.graphs):
@@ -45,9 +78,11 @@ def test_batch_equals_plain_path(setup):
         delta = ops.pdist(dppr, n)
         assert torch.equal(ops.graph_block(gb, bufs["delta"], gi), delta)
         xf = ops.layout(delta, x0[a:a + n].contiguous(), 50)
-        assert torch.equal(bufs["x_out"][a:a + n], xf), f"layout differs for graph {gi} (n={n})"
+        xb = bufs["x_out"][a:a + n]
+        scale = max(1.0, xf.abs().max().item())
+        assert (xb - xf).abs().max().item() <= LAYOUT_REL * scale, f"layout differs for graph {gi} (n={n})"
         st = ops.stress_eval(delta, xf)
-        assert abs(bufs["stress"][gi].item() - st.item()) <= 1e-12 * max(1.0, abs(st.item()))
+        assert abs(bufs["stress"][gi].item() - st.item()) <= STRESS_TRAJ_REL * max(1e-12, abs(st.item()))
 
 
 def test_batch_matches_oracle(setup):

@@ -41,7 +41,9 @@ def test_pdist_matches_oracle(ops, k):
     np.testing.assert_array_equal(got, got.T)  # exactly symmetric
 
 
-@pytest.mark.parametrize("k", [1, 2, 17, 300, 1000])
+# below 1025 nodes the row sweep, from 1025 on the pair-tile sweep (ragged
+# last tile at 1100 and 2000)
+@pytest.mark.parametrize("k", [1, 2, 17, 300, 1000, 1024, 1025, 1100, 2000])
 def test_layout_step_and_stress(ops, k):
     D = synth.random_distance_matrix(k, 200 + k)
     X = synth.uniform_layout(k, 300 + k)
@@ -61,12 +63,13 @@ def test_layout_step_and_stress(ops, k):
     assert np.abs(x1.double().cpu().numpy() - want_x).max() <= STEP_REL * np.abs(want_x).max()
 
 
-def test_layout_coincident_points(ops):
-    k = 40
+@pytest.mark.parametrize("k", [40, 1100])
+def test_layout_coincident_points(ops, k):
     D = synth.random_distance_matrix(k, 5)
     X = synth.uniform_layout(k, 6)
     X[3] = X[7]
     X[10] = X[7]
+    X[k - 1] = X[7]  # a coincident pair across 64-node tiles
     d_t = torch.as_tensor(D, device="cuda")
     x_t = torch.as_tensor(X, device="cuda")
     x1, st = ops.layout_step(d_t, x_t, with_stress=True)
