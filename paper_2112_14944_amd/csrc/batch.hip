@@ -40,6 +40,7 @@ struct BatchPlan {
     int64_t* rt_pre;     // [G+1] prefix of 64-row tiles (sweep finalize items)
     int32_t* rt_graph;   // subgraph of each 64-row tile
     int64_t* pb_pre;     // [G+1] prefix of the partial blocks, T*T*64 floats per subgraph
+    int64_t* iv_pre;     // [G+1] prefix of the 1/Delta pool, k rows of inv_ld(k) floats per subgraph
     int32_t* counter;    // [3] PPR task queue heads, one per tile width
     int32_t* cls_pos;    // [4] first LPT position of the 16-, 32- and 64-column classes, then G
 };
@@ -65,7 +66,12 @@ __device__ __forceinline__ int64_t tiles_of(int n) {
     return cols == 0 ? 0 : (n + cols - 1) / cols;
 }
 
-constexpr int kPlanPrefixes = 6;
+constexpr int kPlanPrefixes = 7;
+
+// Row stride of a subgraph's block in the 1/Delta pool: rows start on a
+// 128-byte boundary, so the 256-byte row segments a pair tile reads span two
+// cache lines, not three.
+__host__ __device__ __forceinline__ int64_t inv_ld(int k) { return ((int64_t)k + 31) / 32 * 32; }
 
 __device__ __forceinline__ int64_t* plan_prefix(const BatchPlan& p, int which) {
     switch (which) {
@@ -74,7 +80,8 @@ __device__ __forceinline__ int64_t* plan_prefix(const BatchPlan& p, int which) {
         case 2: return p.rb_pre;
         case 3: return p.pt_pre;
         case 4: return p.rt_pre;
-        default: return p.pb_pre;
+        case 5: return p.pb_pre;
+        default: return p.iv_pre;
     }
 }
 
@@ -87,7 +94,8 @@ __device__ __forceinline__ int64_t plan_count(int which, int n) {
         case 2: return (n + kLayoutRowsPerBlock - 1) / kLayoutRowsPerBlock;  // stress row blocks
         case 3: return T * (T + 1) / 2;                                      // pair tiles I <= J
         case 4: return T;                                                    // 64-row tiles
-        default: return T * T * kPT;                                         // partial-block floats
+        case 5: return T * T * kPT;                                          // partial-block floats
+        default: return (int64_t)n * inv_ld(n);                              // 1/Delta pool floats
     }
 }
 
@@ -222,7 +230,7 @@ __global__ __launch_bounds__(256) void batch_pdist_kernel(const int64_t* __restr
                                                           const int64_t* __restrict__ pd_pre,
                                                           const int32_t* __restrict__ pd_graph,
                                                           const float* __restrict__ pid, float* __restrict__ delta,
-                                                          float* __restrict__ inv) {
+                                                          const int64_t* __restrict__ iv_pre, float* __restrict__ inv) {
     __shared__ float tt[64][65];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -235,7 +243,8 @@ __global__ __launch_bounds__(256) void batch_pdist_kernel(const int64_t* __restr
         const int64_t i0 = (local / nt) * 64, j0 = (local % nt) * 64;
         const float* P = pid + mat_off[g];
         float* D = delta + mat_off[g];
-        float* V = inv + mat_off[g];
+        float* V = inv + iv_pre[g];
+        const int64_t ldv = inv_ld(k);
         const float hi = pdist_hi(k);
         __syncthreads();
         for (int jj = w; jj < 64; jj += 4) {
@@ -249,7 +258,7 @@ __global__ __launch_bounds__(256) void batch_pdist_kernel(const int64_t* __restr
             const float z = P[i * k + j] + tt[lane][ii];
             const float dv = (i == j) ? 0.f : pdist_value(z, hi);
             D[i * k + j] = dv;
-            V[i * k + j] = (i == j) ? 0.f : __builtin_amdgcn_rcpf(dv);
+            V[i * ldv + j] = (i == j) ? 0.f : __builtin_amdgcn_rcpf(dv);
         }
     }
 }
@@ -263,6 +272,7 @@ __global__ __launch_bounds__(256) void batch_layout_kernel(const int64_t* __rest
                                                            const int64_t* __restrict__ mat_off, int32_t G,
                                                            const int64_t* __restrict__ pre,
                                                            const int32_t* __restrict__ item_graph,
+                                                           const int64_t* __restrict__ iv_pre,
                                                            const float* __restrict__ inv,
                                                            const float2* __restrict__ x, float2* __restrict__ xout,
                                                            float* __restrict__ wsum, double* __restrict__ part) {
@@ -275,7 +285,7 @@ __global__ __launch_bounds__(256) void batch_layout_kernel(const int64_t* __rest
         const int64_t rb = item - pre[g];
         const int64_t nb = node_off[g];
         const int row_begin = (int)(rb * kLayoutRowsPerBlock) + wave * kLayoutRowsPerWave;
-        const double st = layout_rows<MODE, true>(inv + mat_off[g], k, k, x + nb, row_begin,
+        const double st = layout_rows<MODE, true>(inv + iv_pre[g], inv_ld(k), k, x + nb, row_begin,
                                                   xout ? xout + nb : nullptr, 1.f, nullptr, nullptr,
                                                   wsum ? wsum + nb : nullptr);
         if (MODE == kLayoutStress) {
@@ -296,6 +306,7 @@ __global__ __launch_bounds__(256) void batch_pair_kernel(const int64_t* __restri
                                                          const int64_t* __restrict__ pt_pre,
                                                          const int32_t* __restrict__ pt_graph,
                                                          const int64_t* __restrict__ pb_pre,
+                                                         const int64_t* __restrict__ iv_pre,
                                                          const float* __restrict__ inv,
                                                          const float2* __restrict__ x, float* __restrict__ px,
                                                          float* __restrict__ py, float* __restrict__ pw) {
@@ -311,7 +322,7 @@ __global__ __launch_bounds__(256) void batch_pair_kernel(const int64_t* __restri
         int I, J;
         pair_tile_ij((int)(it - pt_pre[g]), I, J);
         const int64_t pb = pb_pre[g];
-        pair_tile<true, MODE>(inv + mat_off[g], k, k, x + node_off[g], I, J, T, px + pb, py + pb, pw + pb,
+        pair_tile<true, MODE>(inv + iv_pre[g], inv_ld(k), k, x + node_off[g], I, J, T, px + pb, py + pb, pw + pb,
                               lds[wave]);
     }
 }
@@ -380,7 +391,8 @@ static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     t.rows = c.template take<RowEnt>((size_t)b->n_nodes);
     t.deg = c.template take<float>((size_t)b->n_nodes);
     t.invd = c.template take<float>((size_t)b->n_nodes);
-    t.inv = c.template take<float>((size_t)std::max<int64_t>(b->pool_size, 1));
+    // 1/Delta pool with rows padded to 32 floats: sum_g k (k + 31) <= pool + 31 n_nodes
+    t.inv = c.template take<float>((size_t)(b->pool_size + 31 * b->n_nodes + 32));
     t.wsum = c.template take<float>((size_t)b->n_nodes);
     t.xtmp = c.template take<float>((size_t)b->n_nodes * 2);
     // row blocks: sum over g of ceil(n_g/16) <= n_nodes/16 + G
@@ -404,6 +416,7 @@ static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     t.plan.rt_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
     t.plan.rt_graph = c.template take<int32_t>((size_t)(b->n_nodes / kPT + b->n_graphs + 1));
     t.plan.pb_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
+    t.plan.iv_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
 
     t.plan.counter = c.template take<int32_t>(64);
     t.plan.cls_pos = c.template take<int32_t>(64);
@@ -480,13 +493,14 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
 
     const unsigned grid = (unsigned)cus * 8;
     hipLaunchKernelGGL(batch_pdist_kernel, dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off, G, w.plan.pd_pre,
-                       w.plan.pd_graph, dppr_pool, delta_pool, w.inv);
+                       w.plan.pd_graph, dppr_pool, delta_pool, w.plan.iv_pre, w.inv);
     const unsigned pgrid = (unsigned)cus * pair_blocks_per_cu<kPairStep>();
     const unsigned wgrid = (unsigned)cus * pair_blocks_per_cu<kPairW>();
     const unsigned fgrid = (unsigned)cus * 8;
     // per-node weight sums, from the pair tiles in the order the sweeps use
     hipLaunchKernelGGL((batch_pair_kernel<kPairW>), dim3(wgrid), dim3(256), 0, s, b->node_off, b->mat_off, G,
-                       w.plan.pt_pre, w.plan.pt_graph, w.plan.pb_pre, w.inv, reinterpret_cast<const float2*>(x0),
+                       w.plan.pt_pre, w.plan.pt_graph, w.plan.pb_pre, w.plan.iv_pre, w.inv,
+                       reinterpret_cast<const float2*>(x0),
                        w.px, w.py, w.pw);
     hipLaunchKernelGGL((batch_pair_finalize_kernel<kPairW>), dim3(fgrid), dim3(256), 0, s, b->node_off, G,
                        w.plan.rt_pre, w.plan.rt_graph, w.plan.pb_pre, w.px, w.py, w.pw,
@@ -504,7 +518,8 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     for (int it = 0; it < stress_iters; ++it) {
         float2* out = bufs[next];
         hipLaunchKernelGGL((batch_pair_kernel<kPairStep>), dim3(pgrid), dim3(256), 0, s, b->node_off, b->mat_off,
-                           G, w.plan.pt_pre, w.plan.pt_graph, w.plan.pb_pre, w.inv, cur, w.px, w.py, w.pw);
+                           G, w.plan.pt_pre, w.plan.pt_graph, w.plan.pb_pre, w.plan.iv_pre, w.inv, cur, w.px, w.py,
+                           w.pw);
         hipLaunchKernelGGL((batch_pair_finalize_kernel<kPairStep>), dim3(fgrid), dim3(256), 0, s, b->node_off, G,
                            w.plan.rt_pre, w.plan.rt_graph, w.plan.pb_pre, w.px, w.py, w.pw, cur, out, w.wsum);
         cur = out;
@@ -512,7 +527,7 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     }
     if (stress_out) {
         hipLaunchKernelGGL((batch_layout_kernel<kLayoutStress>), dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off,
-                           G, w.plan.rb_pre, w.plan.rb_graph, w.inv, cur, nullptr, nullptr, w.part);
+                           G, w.plan.rb_pre, w.plan.rb_graph, w.plan.iv_pre, w.inv, cur, nullptr, nullptr, w.part);
         hipLaunchKernelGGL(batch_stress_sum_kernel, dim3((G + 255) / 256), dim3(256), 0, s, w.plan.rb_pre, G, w.part,
                            stress_out);
     }
