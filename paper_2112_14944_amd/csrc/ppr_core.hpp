@@ -18,10 +18,10 @@
 
 namespace pprviz {
 
-// 768 threads (12 waves, 3 per SIMD) leave each wave 168 VGPRs.
-constexpr int kResThreads = 768;
+// 1024 threads (16 waves, 4 per SIMD) leave each wave 128 VGPRs.
+constexpr int kResThreads = 1024;
 constexpr int kResWaves = kResThreads / kWave;
-constexpr int kResMaxK = 12;  // rows per lane (4 columns each) held in registers across a step
+constexpr int kResMaxK = 9;  // rows per lane (4 columns each) held in registers across a step
 
 // Tile geometry.  Lanes work in quads: a quad owns 16 columns of one row, each
 // lane 4 consecutive columns read with one 16-byte LDS load per arc, and the
