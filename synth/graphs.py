@@ -113,7 +113,7 @@ def build_graph(n: int, eu, ev, weight=None) -> Graph:
     src = np.concatenate([a, b])
     dst = np.concatenate([b, a])
     eid = np.concatenate([np.arange(m), np.arange(m)])
-    order = np.lexsort((dst, src))
+    order = np.argsort(src * n + dst)  # by (src, dst); the pairs are unique
     src, dst, eid = src[order], dst[order], eid[order]
     counts = np.bincount(src, minlength=n)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
@@ -163,9 +163,18 @@ def chung_lu(n: int, gamma: float, avg_degree: float, seed: int) -> Graph:
     m = int(rng.poisson(total / 2.0))
     cdf = np.cumsum(w / total)
     cdf[-1] = 1.0
-    u = np.searchsorted(cdf, rng.random(m), side="right")
-    v = np.searchsorted(cdf, rng.random(m), side="right")
+    u = _inverse_cdf(cdf, rng.random(m))
+    v = _inverse_cdf(cdf, rng.random(m))
     return build_graph(n, u, v)
+
+
+def _inverse_cdf(cdf, r):
+    """searchsorted(cdf, r, side="right"), with the queries visited in sorted
+    order (same result, far fewer cache misses for millions of queries)."""
+    order = np.argsort(r)
+    out = np.empty(r.shape[0], dtype=np.int64)
+    out[order] = np.searchsorted(cdf, r[order], side="right")
+    return out
 
 
 def sbm(block_sizes, p_in: float, p_out: float, seed: int, weighted=None) -> Graph:
