@@ -303,7 +303,8 @@ __global__ __launch_bounds__(256) void batch_layout_kernel(const int64_t* __rest
 // At least 5 waves per SIMD (96 VGPRs): the chunk loads in flight need the
 // occupancy more than the scheduler needs the registers.
 template <int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_pair_kernel(const int64_t* __restrict__ node_off,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8)))
+void batch_pair_kernel(const int64_t* __restrict__ node_off,
                                                          const int64_t* __restrict__ mat_off, int32_t G,
                                                          const int64_t* __restrict__ pt_pre,
                                                          const int32_t* __restrict__ pt_graph,
