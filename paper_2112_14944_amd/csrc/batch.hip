@@ -376,6 +376,7 @@ __global__ void copy_kernel(const float* __restrict__ a, float* __restrict__ b, 
 
 struct BatchWs {
     RowEnt* rows;
+    int32_t* col_r;  // arcs in bank-class order (row_table_kernel)
     float* deg;
     float* invd;
     float* inv;   // 1/Delta pool (zero diagonal)
@@ -392,6 +393,7 @@ template <typename Cursor>
 static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     BatchWs t;
     t.rows = c.template take<RowEnt>((size_t)b->n_nodes);
+    t.col_r = c.template take<int32_t>((size_t)std::max<int64_t>(b->nnz, 1));
     t.deg = c.template take<float>((size_t)b->n_nodes);
     t.invd = c.template take<float>((size_t)b->n_nodes);
     // 1/Delta pool with rows padded to 32 floats: sum_g k (k + 31) <= pool + 31 n_nodes
@@ -467,7 +469,7 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     const int G = b->n_graphs;
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[0], s));
     launch_degree(b->row_ptr, nullptr, b->n_nodes, w.deg, w.invd, s);
-    launch_row_table(b->row_ptr, b->node_off, 0, G, w.rows, s);
+    launch_row_table(b->row_ptr, b->col_idx, nullptr, b->node_off, 0, G, w.rows, w.col_r, nullptr, s);
     hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, b->node_off, G, w.plan);
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[1], s));
 
@@ -477,7 +479,7 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     ba.G = G;
     ba.r.rows = w.rows;
     ba.r.row_ptr = b->row_ptr;
-    ba.r.col_idx = b->col_idx;
+    ba.r.col_idx = w.col_r;
     ba.r.weight = nullptr;
     ba.r.invd = w.invd;
     ba.r.deg = w.deg;

@@ -99,6 +99,8 @@ struct BwdWs {
     float* pi;
     double* part;
     int32_t* hist;
+    int32_t* col_r;  // recompute on the resident path: arcs in bank-class order
+    float* w_r;
     double* dq;
     double* dd;
     double* g;
@@ -117,6 +119,9 @@ static void bwd_layout(Cursor& c, int n, int64_t nnz, bool recompute, BwdWs* w) 
     t.pi = recompute ? c.template take<float>((size_t)n * n) : nullptr;
     t.part = c.template take<double>((size_t)stream_resid_chunks(n) * ld);
     t.hist = c.template take<int32_t>(kDegKeys);
+    const bool res = recompute && use_resident(n);
+    t.col_r = res ? c.template take<int32_t>((size_t)std::max<int64_t>(nnz, 1)) : nullptr;
+    t.w_r = res ? c.template take<float>((size_t)std::max<int64_t>(nnz, 1)) : nullptr;
     t.dq = c.template take<double>((size_t)std::max<int64_t>(nnz, 1));
     t.dd = c.template take<double>(n);
     t.g = c.template take<double>((size_t)std::max<int64_t>(nnz, 1));
@@ -157,8 +162,8 @@ ppr_status ppr_matrix_backward(const ppr_csr* g, float alpha, int32_t T, const f
     launch_degree(g->row_ptr, g->weight, n, w.deg, w.invd, s);
     const float* pi = ppr;
     if (recompute) {
-        ppr_forward(g, nullptr, n, nullptr, n, alpha, T, w.pi, nullptr, w.deg, w.invd, nullptr, w.rows, w.hist, w.ya,
-                    w.yb, w.part, s);
+        ppr_forward(g, nullptr, n, nullptr, n, alpha, T, w.pi, nullptr, w.deg, w.invd, nullptr, w.rows, w.col_r,
+                    w.w_r, w.hist, w.ya, w.yb, w.part, s);
         pi = w.pi;
     }
     stream_row_order(g->row_ptr, n, w.hist, w.rows, s);

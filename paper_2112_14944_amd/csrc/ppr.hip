@@ -27,9 +27,21 @@ __global__ void degree_kernel(const int32_t* __restrict__ row_ptr, const float* 
     invd[v] = (re > rs && d > 0.f) ? 1.0f / d : 1.0f;
 }
 
+// Row table of the resident tile (rows sorted by degree, longest first, ties
+// by row id; one block per graph), and a copy of the arcs with each row's arcs
+// dealt by LDS bank class.  In the tile, the four quads of a 16-lane LDS pass
+// read the rows of four consecutive slot positions, arc position m of each at
+// the same instruction, and a row u of a 16- (32-) column tile starts in bank
+// group u mod 4 (u mod 2).  Position m of the row in slot p therefore takes an
+// arc of class (m + p) mod 4 (mod 2) while that class lasts, so the four reads
+// of a pass fall in different bank groups.  Only the order of each row's arcs
+// changes (and with it the order of the FP32 sum).
 __global__ __launch_bounds__(256) void row_table_kernel(const int32_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col_idx,
+                                                       const float* __restrict__ weight,
                                                        const int64_t* __restrict__ node_off, int32_t n_single,
-                                                       RowEnt* __restrict__ table) {
+                                                       RowEnt* __restrict__ table, int32_t* __restrict__ col_out,
+                                                       float* __restrict__ w_out) {
     constexpr int kMaxRows = 4096;
     __shared__ uint32_t key[kMaxRows];
     const int g = blockIdx.x;
@@ -64,15 +76,44 @@ __global__ __launch_bounds__(256) void row_table_kernel(const int32_t* __restric
             __syncthreads();
         }
     }
-    for (int i = threadIdx.x; i < n; i += 256) {
-        const int v = (int)(key[i] & 4095u);
-        table[base + i] = RowEnt{row_ptr[base + v], row_ptr[base + v + 1], v, 0};
+    const int cols = res_cols_for(n);
+    const int M = cols == 16 ? 4 : (cols == 32 ? 2 : 1);  // bank classes
+    for (int p = threadIdx.x; p < n; p += 256) {
+        const int v = (int)(key[p] & 4095u);
+        const int rs = row_ptr[base + v], re = row_ptr[base + v + 1];
+        table[base + p] = RowEnt{rs, re, v, 0};
+        if (M == 1) {
+            for (int e = rs; e < re; ++e) {
+                col_out[e] = col_idx[e];
+                if (w_out) w_out[e] = weight[e];
+            }
+            continue;
+        }
+        // next[c]: next arc of class c in the original order (re when none)
+        int next[4];
+        for (int c = 0; c < 4; ++c) {
+            int e = rs;
+            while (e < re && (int)((col_idx[e] - base) & (M - 1)) != c) ++e;
+            next[c] = c < M ? e : re;
+        }
+        for (int m = rs; m < re; ++m) {
+            int c = (m - rs + p) & (M - 1);
+            for (int t = 0; t < M && next[c] >= re; ++t) c = (c + 1) & (M - 1);
+            const int e = next[c];
+            col_out[m] = col_idx[e];
+            if (w_out) w_out[m] = weight[e];
+            int f = e + 1;
+            while (f < re && (int)((col_idx[f] - base) & (M - 1)) != c) ++f;
+            next[c] = f;
+        }
     }
 }
 
-void launch_row_table(const int32_t* row_ptr, const int64_t* node_off, int32_t n_single, int32_t blocks,
-                      RowEnt* table, hipStream_t s) {
-    hipLaunchKernelGGL(row_table_kernel, dim3(blocks), dim3(256), 0, s, row_ptr, node_off, n_single, table);
+void launch_row_table(const int32_t* row_ptr, const int32_t* col_idx, const float* weight,
+                      const int64_t* node_off, int32_t n_single, int32_t blocks, RowEnt* table, int32_t* col_out,
+                      float* w_out, hipStream_t s) {
+    hipLaunchKernelGGL(row_table_kernel, dim3(blocks), dim3(256), 0, s, row_ptr, col_idx, weight, node_off,
+                       n_single, table, col_out, w_out);
 }
 
 template <int COLS, bool WEIGHTED>
@@ -115,6 +156,8 @@ struct PprWs {
     float* yb;
     double* part;
     int32_t* hist;
+    int32_t* col_r;  // resident path: arcs in bank-class order
+    float* w_r;
 };
 
 ppr_status validate_csr(const ppr_csr* g) {
@@ -130,15 +173,16 @@ bool use_resident(int n) { return res_cols_for(n) != 0; }
 // the LDS-resident kernel.
 void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int32_t* tgt, int32_t n_tgt,
                  float alpha, int32_t T, float* ppr_out, float* dppr_out, const float* deg, const float* invd,
-                 double* resid, RowEnt* rows, int32_t* hist, float* ya, float* yb, double* part, hipStream_t s) {
+                 double* resid, RowEnt* rows, int32_t* col_r, float* w_r, int32_t* hist, float* ya, float* yb,
+                 double* part, hipStream_t s) {
     const int n = g->n;
     if (use_resident(n)) {
-        launch_row_table(g->row_ptr, nullptr, n, 1, rows, s);
+        launch_row_table(g->row_ptr, g->col_idx, g->weight, nullptr, n, 1, rows, col_r, g->weight ? w_r : nullptr, s);
         ResArgs a;
         a.rows = rows;
         a.row_ptr = g->row_ptr;
-        a.col_idx = g->col_idx;
-        a.weight = g->weight;
+        a.col_idx = col_r;
+        a.weight = g->weight ? w_r : nullptr;
         a.invd = invd;
         a.deg = deg;
         a.src = src;
@@ -177,7 +221,7 @@ void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int3
 }
 
 template <typename Cursor>
-static void ppr_ws_layout(Cursor& c, int n, int n_src, PprWs* w) {
+static void ppr_ws_layout(Cursor& c, int n, int64_t nnz, bool weighted, int n_src, PprWs* w) {
     auto* rows = c.template take<RowEnt>(n);
     auto* deg = c.template take<float>(n);
     auto* invd = c.template take<float>(n);
@@ -190,6 +234,16 @@ static void ppr_ws_layout(Cursor& c, int n, int n_src, PprWs* w) {
         w->ya = w->yb = nullptr;
         w->part = nullptr;
         w->hist = nullptr;
+        w->col_r = nullptr;
+        w->w_r = nullptr;
+    }
+    if (use_resident(n)) {
+        auto* col_r = c.template take<int32_t>((size_t)std::max<int64_t>(nnz, 1));
+        auto* w_r = weighted ? c.template take<float>((size_t)std::max<int64_t>(nnz, 1)) : nullptr;
+        if (w) {
+            w->col_r = col_r;
+            w->w_r = w_r;
+        }
     }
     if (!use_resident(n)) {
         const int64_t ldy = stream_ld(n_src);
@@ -261,7 +315,7 @@ size_t ppr_matrix_workspace(const ppr_csr* g, int32_t n_src, int32_t n_tgt) {
     (void)n_tgt;
     if (g == nullptr || g->n < 1 || n_src < 0) return 0;
     WsSize c;
-    ppr_ws_layout(c, g->n, n_src, nullptr);
+    ppr_ws_layout(c, g->n, g->nnz, g->weight != nullptr, n_src, nullptr);
     return c.used;
 }
 
@@ -283,15 +337,15 @@ ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src, const
     if (n_src == 0) return conv ? PPR_OK : PPR_ENOCONV;
     WsCursor cur{static_cast<char*>(ws), ws_bytes};
     PprWs w;
-    ppr_ws_layout(cur, g->n, n_src, &w);
+    ppr_ws_layout(cur, g->n, g->nnz, g->weight != nullptr, n_src, &w);
     if (ws == nullptr || cur.used > ws_bytes) return PPR_EWORKSPACE;
     if (pending_error() != PPR_OK) return PPR_EHIP;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int n = g->n;
     launch_degree(g->row_ptr, g->weight, n, w.deg, w.invd, s);
 
-    ppr_forward(g, src, n_src, tgt, n_tgt, alpha, T, ppr_out, dppr_out, w.deg, w.invd, w.resid, w.rows, w.hist, w.ya,
-                w.yb, w.part, s);
+    ppr_forward(g, src, n_src, tgt, n_tgt, alpha, T, ppr_out, dppr_out, w.deg, w.invd, w.resid, w.rows, w.col_r,
+                w.w_r, w.hist, w.ya, w.yb, w.part, s);
     st = launch_status();
     if (st != PPR_OK) return st;
     if (resid_out) {
