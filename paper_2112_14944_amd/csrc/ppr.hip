@@ -35,7 +35,8 @@ __global__ void degree_kernel(const int32_t* __restrict__ row_ptr, const float* 
 // group u mod 4 (u mod 2).  Position m of the row in slot p therefore takes an
 // arc of class (m + p) mod 4 (mod 2) while that class lasts, so the four reads
 // of a pass fall in different bank groups.  Only the order of each row's arcs
-// changes (and with it the order of the FP32 sum).
+// changes (and with it the order of the FP32 sum).  The copy holds each
+// arc's LDS byte offset in the tile, (u - first node) * 4 COLS, not its node id.
 __global__ __launch_bounds__(256) void row_table_kernel(const int32_t* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ col_idx,
                                                        const float* __restrict__ weight,
@@ -78,13 +79,14 @@ __global__ __launch_bounds__(256) void row_table_kernel(const int32_t* __restric
     }
     const int cols = res_cols_for(n);
     const int M = cols == 16 ? 4 : (cols == 32 ? 2 : 1);  // bank classes
+    const int stride = (cols > 0 ? cols : 16) * 4;        // LDS bytes per row
     for (int p = threadIdx.x; p < n; p += 256) {
         const int v = (int)(key[p] & 4095u);
         const int rs = row_ptr[base + v], re = row_ptr[base + v + 1];
         table[base + p] = RowEnt{rs, re, v, 0};
         if (M == 1) {
             for (int e = rs; e < re; ++e) {
-                col_out[e] = col_idx[e];
+                col_out[e] = (int)(col_idx[e] - base) * stride;
                 if (w_out) w_out[e] = weight[e];
             }
             continue;
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(256) void row_table_kernel(const int32_t* __restric
             int c = (m - rs + p) & (M - 1);
             for (int t = 0; t < M && next[c] >= re; ++t) c = (c + 1) & (M - 1);
             const int e = next[c];
-            col_out[m] = col_idx[e];
+            col_out[m] = (int)(col_idx[e] - base) * stride;
             if (w_out) w_out[m] = weight[e];
             int f = e + 1;
             while (f < re && (int)((col_idx[f] - base) & (M - 1)) != c) ++f;

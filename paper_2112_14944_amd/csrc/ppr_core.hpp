@@ -78,7 +78,7 @@ __device__ __forceinline__ RowEnt load_row(gcptr<RowEnt> p, int64_t i) {
 struct ResArgs {
     const RowEnt* rows;      // per graph, rows in slot order (row_table_kernel)
     const int32_t* row_ptr;  // global CSR row pointers
-    const int32_t* col_idx;  // global node ids
+    const int32_t* col_idx;  // per arc (bank-class order): LDS byte offset of the neighbour's row
     const float* weight;     // arc weights, or nullptr
     const float* invd;       // per global node: 1/d, or 1 for a node without arcs
     const float* deg;        // per global node: weighted degree d
@@ -171,9 +171,10 @@ struct ResLds {
 
 // Loads one 16-arc chunk of a quad's row (arcs e0 + 4i + q for i = 0..3).
 template <bool WEIGHTED>
-__device__ __forceinline__ void load_chunk(gcptr<int32_t> pc, gcptr<float> pw, int e0, int re, int q, int& r0,
-                                           int& r1, int& r2, int& r3, float& w0, float& w1, float& w2,
+__device__ __forceinline__ void load_chunk(gcptr<int32_t> pc, gcptr<float> pw, int e0, int re, int q, int dummy,
+                                           int& r0, int& r1, int& r2, int& r3, float& w0, float& w1, float& w2,
                                            float& w3) {
+    r0 = r1 = r2 = r3 = dummy;
     if (e0 + q < re) r0 = pc[e0 + q];
     if (e0 + 4 + q < re) r1 = pc[e0 + 4 + q];
     if (e0 + 8 + q < re) r2 = pc[e0 + 8 + q];
@@ -247,7 +248,6 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
     for (int it = 1; it < a.T; ++it) {
         const int r0 = opaque(row0);
         const int64_t b = opaque_s(base);
-        const int bi = (int)b;
         const int n = opaque_s32(t.n);
         const int dummy = n * STRIDE;
         // Rows are visited in slot order (degree-sorted, so the rows that
@@ -259,7 +259,7 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
         if (r0 + RPP < n) e2 = load_row(rows, b + r0 + RPP);
         int p0 = 0, p1 = 0, p2 = 0, p3 = 0;
         float pw0 = 0.f, pw1 = 0.f, pw2 = 0.f, pw3 = 0.f;
-        load_chunk<WEIGHTED>(pc, pw, e1.rs, e1.re, q, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
+        load_chunk<WEIGHTED>(pc, pw, e1.rs, e1.re, q, dummy, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
 #pragma unroll
         for (int k = 0; k < kResMaxK; ++k) {
             if (k * RPP < n) {
@@ -269,18 +269,14 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
                 const float cw0 = pw0, cw1 = pw1, cw2 = pw2, cw3 = pw3;
                 e1 = e2;
                 if (k + 1 < kResMaxK && slot + RPP < n)
-                    load_chunk<WEIGHTED>(pc, pw, e1.rs, e1.re, q, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
+                    load_chunk<WEIGHTED>(pc, pw, e1.rs, e1.re, q, dummy, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
                 if (k + 2 < kResMaxK && slot + 2 * RPP < n) e2 = load_row(rows, b + slot + 2 * RPP);
                 if (slot < n) {
                     vs[k] = v;
                     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
                     if (rs == re) acc = lds_load4(lds, v * STRIDE + cbyte);
                     if (rs < re) {
-                        gather_chunk<WEIGHTED, 4>(lds, rs + q < re ? (c0 - bi) * STRIDE : dummy,
-                                                  rs + 4 + q < re ? (c1 - bi) * STRIDE : dummy,
-                                                  rs + 8 + q < re ? (c2 - bi) * STRIDE : dummy,
-                                                  rs + 12 + q < re ? (c3 - bi) * STRIDE : dummy, cw0, cw1, cw2,
-                                                  cw3, cbyte, acc);
+                        gather_chunk<WEIGHTED, 4>(lds, c0, c1, c2, c3, cw0, cw1, cw2, cw3, cbyte, acc);
                     }
                     // further chunks of rows longer than 16 arcs; a tail of
                     // at most 8 arcs takes a half chunk
@@ -288,15 +284,11 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
                     for (int e0 = rs + 16; e0 < re; e0 += 16) {
                         int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
                         float dw0 = 0.f, dw1 = 0.f, dw2 = 0.f, dw3 = 0.f;
-                        load_chunk<WEIGHTED>(pc, pw, e0, re, q, d0, d1, d2, d3, dw0, dw1, dw2, dw3);
-                        const int a0 = e0 + q < re ? (d0 - bi) * STRIDE : dummy;
-                        const int a1 = e0 + 4 + q < re ? (d1 - bi) * STRIDE : dummy;
+                        load_chunk<WEIGHTED>(pc, pw, e0, re, q, dummy, d0, d1, d2, d3, dw0, dw1, dw2, dw3);
                         if (re - e0 > 8) {
-                            gather_chunk<WEIGHTED, 4>(lds, a0, a1, e0 + 8 + q < re ? (d2 - bi) * STRIDE : dummy,
-                                                      e0 + 12 + q < re ? (d3 - bi) * STRIDE : dummy, dw0, dw1,
-                                                      dw2, dw3, cbyte, acc);
+                            gather_chunk<WEIGHTED, 4>(lds, d0, d1, d2, d3, dw0, dw1, dw2, dw3, cbyte, acc);
                         } else {
-                            gather_chunk<WEIGHTED, 2>(lds, a0, a1, dummy, dummy, dw0, dw1, 0.f, 0.f, cbyte, acc);
+                            gather_chunk<WEIGHTED, 2>(lds, d0, d1, dummy, dummy, dw0, dw1, 0.f, 0.f, cbyte, acc);
                         }
                     }
                     acc.x += v == msrc[0] ? alpha : 0.f;
