@@ -393,7 +393,7 @@ template <typename Cursor>
 static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     BatchWs t;
     t.rows = c.template take<RowEnt>((size_t)b->n_nodes);
-    t.col_r = c.template take<int32_t>((size_t)std::max<int64_t>(b->nnz, 1));
+    t.col_r = c.template take<int32_t>((size_t)(b->nnz + kArcPad));
     t.deg = c.template take<float>((size_t)b->n_nodes);
     t.invd = c.template take<float>((size_t)b->n_nodes);
     // 1/Delta pool with rows padded to 32 floats: sum_g k (k + 31) <= pool + 31 n_nodes

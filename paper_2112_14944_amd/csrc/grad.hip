@@ -120,8 +120,8 @@ static void bwd_layout(Cursor& c, int n, int64_t nnz, bool recompute, BwdWs* w) 
     t.part = c.template take<double>((size_t)stream_resid_chunks(n) * ld);
     t.hist = c.template take<int32_t>(kDegKeys);
     const bool res = recompute && use_resident(n);
-    t.col_r = res ? c.template take<int32_t>((size_t)std::max<int64_t>(nnz, 1)) : nullptr;
-    t.w_r = res ? c.template take<float>((size_t)std::max<int64_t>(nnz, 1)) : nullptr;
+    t.col_r = res ? c.template take<int32_t>((size_t)(nnz + kArcPad)) : nullptr;
+    t.w_r = res ? c.template take<float>((size_t)(nnz + kArcPad)) : nullptr;
     t.dq = c.template take<double>((size_t)std::max<int64_t>(nnz, 1));
     t.dd = c.template take<double>(n);
     t.g = c.template take<double>((size_t)std::max<int64_t>(nnz, 1));

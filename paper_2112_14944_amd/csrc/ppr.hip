@@ -240,8 +240,8 @@ static void ppr_ws_layout(Cursor& c, int n, int64_t nnz, bool weighted, int n_sr
         w->w_r = nullptr;
     }
     if (use_resident(n)) {
-        auto* col_r = c.template take<int32_t>((size_t)std::max<int64_t>(nnz, 1));
-        auto* w_r = weighted ? c.template take<float>((size_t)std::max<int64_t>(nnz, 1)) : nullptr;
+        auto* col_r = c.template take<int32_t>((size_t)(nnz + kArcPad));
+        auto* w_r = weighted ? c.template take<float>((size_t)(nnz + kArcPad)) : nullptr;
         if (w) {
             w->col_r = col_r;
             w->w_r = w_r;

@@ -21,6 +21,7 @@ namespace pprviz {
 // 1024 threads (16 waves, 4 per SIMD) leave each wave 128 VGPRs.
 constexpr int kResThreads = 1024;
 constexpr int kResWaves = kResThreads / kWave;
+constexpr int kArcPad = 16;  // padding entries after the tile's arc array (chunk loads read ahead)
 constexpr int kResMaxK = 9;  // rows per lane (4 columns each) held in registers across a step
 
 // Tile geometry.  Lanes work in quads: a quad owns 16 columns of one row, each
@@ -78,7 +79,7 @@ __device__ __forceinline__ RowEnt load_row(gcptr<RowEnt> p, int64_t i) {
 struct ResArgs {
     const RowEnt* rows;      // per graph, rows in slot order (row_table_kernel)
     const int32_t* row_ptr;  // global CSR row pointers
-    const int32_t* col_idx;  // per arc (bank-class order): LDS byte offset of the neighbour's row
+    const int32_t* col_idx;  // per arc (bank-class order, 16 entries of padding): LDS byte offset of the neighbour's row
     const float* weight;     // arc weights, or nullptr
     const float* invd;       // per global node: 1/d, or 1 for a node without arcs
     const float* deg;        // per global node: weighted degree d
@@ -105,17 +106,17 @@ __device__ __forceinline__ float4 lds_load4(const float* lds, int byte_off) {
     return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(lds) + byte_off);
 }
 
-// One chunk of 16 arcs (NW = 4 words) or 8 arcs (NW = 2) of a quad's row: arc
-// m sits in lane m%4, word m/4 (a0..a3 hold LDS byte offsets of the
-// neighbours' rows, a zero row past the row's end).  Eight 16-byte reads are
-// issued before their adds.
-template <bool WEIGHTED, int NW>
+// One chunk of 16 arcs (NH = 2 halves) or 8 arcs (NH = 1) of a quad's row:
+// arc 4L + W sits in lane L, word W (a0..a3 hold LDS byte offsets of the
+// neighbours' rows, the zero row past the row's end), so the arcs are summed
+// in row order.  Eight 16-byte reads are issued before their adds.
+template <bool WEIGHTED, int NH>
 __device__ __forceinline__ void gather_chunk(const float* __restrict__ lds, int a0, int a1, int a2, int a3,
                                              float w0, float w1, float w2, float w3, int cbyte, float4& acc) {
-#define PPRVIZ_RD(M, A) y[(M) & 7] = lds_load4(lds, quad_bcast<(M) % 4>(A) + cbyte);
+#define PPRVIZ_RD(M, A) y[(M) & 7] = lds_load4(lds, quad_bcast<(M) / 4>(A) + cbyte);
 #define PPRVIZ_ACC(M, W)                                          \
     if (WEIGHTED) {                                               \
-        const float ww = quad_bcast<(M) % 4>(W);                  \
+        const float ww = quad_bcast<(M) / 4>(W);                  \
         acc.x = fmaf(ww, y[(M) & 7].x, acc.x);                    \
         acc.y = fmaf(ww, y[(M) & 7].y, acc.y);                    \
         acc.z = fmaf(ww, y[(M) & 7].z, acc.z);                    \
@@ -127,18 +128,18 @@ __device__ __forceinline__ void gather_chunk(const float* __restrict__ lds, int 
         acc.w += y[(M) & 7].w;                                    \
     }
     float4 y[8];
-    PPRVIZ_RD(0, a0) PPRVIZ_RD(1, a0) PPRVIZ_RD(2, a0) PPRVIZ_RD(3, a0)
-    PPRVIZ_RD(4, a1) PPRVIZ_RD(5, a1) PPRVIZ_RD(6, a1) PPRVIZ_RD(7, a1)
+    PPRVIZ_RD(0, a0) PPRVIZ_RD(1, a1) PPRVIZ_RD(2, a2) PPRVIZ_RD(3, a3)
+    PPRVIZ_RD(4, a0) PPRVIZ_RD(5, a1) PPRVIZ_RD(6, a2) PPRVIZ_RD(7, a3)
     __builtin_amdgcn_sched_barrier(0);
-    PPRVIZ_ACC(0, w0) PPRVIZ_ACC(1, w0) PPRVIZ_ACC(2, w0) PPRVIZ_ACC(3, w0)
-    PPRVIZ_ACC(4, w1) PPRVIZ_ACC(5, w1) PPRVIZ_ACC(6, w1) PPRVIZ_ACC(7, w1)
-    if (NW == 2) return;
+    PPRVIZ_ACC(0, w0) PPRVIZ_ACC(1, w1) PPRVIZ_ACC(2, w2) PPRVIZ_ACC(3, w3)
+    PPRVIZ_ACC(4, w0) PPRVIZ_ACC(5, w1) PPRVIZ_ACC(6, w2) PPRVIZ_ACC(7, w3)
+    if (NH == 1) return;
     __builtin_amdgcn_sched_barrier(0);
-    PPRVIZ_RD(8, a2) PPRVIZ_RD(9, a2) PPRVIZ_RD(10, a2) PPRVIZ_RD(11, a2)
-    PPRVIZ_RD(12, a3) PPRVIZ_RD(13, a3) PPRVIZ_RD(14, a3) PPRVIZ_RD(15, a3)
+    PPRVIZ_RD(8, a0) PPRVIZ_RD(9, a1) PPRVIZ_RD(10, a2) PPRVIZ_RD(11, a3)
+    PPRVIZ_RD(12, a0) PPRVIZ_RD(13, a1) PPRVIZ_RD(14, a2) PPRVIZ_RD(15, a3)
     __builtin_amdgcn_sched_barrier(0);
-    PPRVIZ_ACC(8, w2) PPRVIZ_ACC(9, w2) PPRVIZ_ACC(10, w2) PPRVIZ_ACC(11, w2)
-    PPRVIZ_ACC(12, w3) PPRVIZ_ACC(13, w3) PPRVIZ_ACC(14, w3) PPRVIZ_ACC(15, w3)
+    PPRVIZ_ACC(8, w0) PPRVIZ_ACC(9, w1) PPRVIZ_ACC(10, w2) PPRVIZ_ACC(11, w3)
+    PPRVIZ_ACC(12, w0) PPRVIZ_ACC(13, w1) PPRVIZ_ACC(14, w2) PPRVIZ_ACC(15, w3)
 #undef PPRVIZ_RD
 #undef PPRVIZ_ACC
 }
@@ -174,16 +175,21 @@ template <bool WEIGHTED>
 __device__ __forceinline__ void load_chunk(gcptr<int32_t> pc, gcptr<float> pw, int e0, int re, int q, int dummy,
                                            int& r0, int& r1, int& r2, int& r3, float& w0, float& w1, float& w2,
                                            float& w3) {
-    r0 = r1 = r2 = r3 = dummy;
-    if (e0 + q < re) r0 = pc[e0 + q];
-    if (e0 + 4 + q < re) r1 = pc[e0 + 4 + q];
-    if (e0 + 8 + q < re) r2 = pc[e0 + 8 + q];
-    if (e0 + 12 + q < re) r3 = pc[e0 + 12 + q];
+    // lane q takes the 4 consecutive arcs e0 + 4q .. e0 + 4q + 3; the arc
+    // array is padded by 16 entries, so the loads need no guard
+    const int e = e0 + 4 * q;
+    const int lim = re - e;
+    const int v0 = pc[e], v1 = pc[e + 1], v2 = pc[e + 2], v3 = pc[e + 3];
+    r0 = lim > 0 ? v0 : dummy;
+    r1 = lim > 1 ? v1 : dummy;
+    r2 = lim > 2 ? v2 : dummy;
+    r3 = lim > 3 ? v3 : dummy;
     if (WEIGHTED) {
-        w0 = e0 + q < re ? pw[e0 + q] : 0.f;
-        w1 = e0 + 4 + q < re ? pw[e0 + 4 + q] : 0.f;
-        w2 = e0 + 8 + q < re ? pw[e0 + 8 + q] : 0.f;
-        w3 = e0 + 12 + q < re ? pw[e0 + 12 + q] : 0.f;
+        const float u0 = pw[e], u1 = pw[e + 1], u2 = pw[e + 2], u3 = pw[e + 3];
+        w0 = lim > 0 ? u0 : 0.f;
+        w1 = lim > 1 ? u1 : 0.f;
+        w2 = lim > 2 ? u2 : 0.f;
+        w3 = lim > 3 ? u3 : 0.f;
     }
 }
 
@@ -276,7 +282,7 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
                     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
                     if (rs == re) acc = lds_load4(lds, v * STRIDE + cbyte);
                     if (rs < re) {
-                        gather_chunk<WEIGHTED, 4>(lds, c0, c1, c2, c3, cw0, cw1, cw2, cw3, cbyte, acc);
+                        gather_chunk<WEIGHTED, 2>(lds, c0, c1, c2, c3, cw0, cw1, cw2, cw3, cbyte, acc);
                     }
                     // further chunks of rows longer than 16 arcs; a tail of
                     // at most 8 arcs takes a half chunk
@@ -286,9 +292,9 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
                         float dw0 = 0.f, dw1 = 0.f, dw2 = 0.f, dw3 = 0.f;
                         load_chunk<WEIGHTED>(pc, pw, e0, re, q, dummy, d0, d1, d2, d3, dw0, dw1, dw2, dw3);
                         if (re - e0 > 8) {
-                            gather_chunk<WEIGHTED, 4>(lds, d0, d1, d2, d3, dw0, dw1, dw2, dw3, cbyte, acc);
+                            gather_chunk<WEIGHTED, 2>(lds, d0, d1, d2, d3, dw0, dw1, dw2, dw3, cbyte, acc);
                         } else {
-                            gather_chunk<WEIGHTED, 2>(lds, d0, d1, dummy, dummy, dw0, dw1, 0.f, 0.f, cbyte, acc);
+                            gather_chunk<WEIGHTED, 1>(lds, d0, d1, d2, d3, dw0, dw1, dw2, dw3, cbyte, acc);
                         }
                     }
                     acc.x += v == msrc[0] ? alpha : 0.f;
