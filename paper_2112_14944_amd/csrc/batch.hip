@@ -376,7 +376,7 @@ __global__ void copy_kernel(const float* __restrict__ a, float* __restrict__ b, 
 
 struct BatchWs {
     RowEnt* rows;
-    int32_t* col_r;  // arcs in bank-class order (row_table_kernel)
+    int32_t* col_r;  // arcs in bank-class order (bank_order_kernel)
     float* deg;
     float* invd;
     float* inv;   // 1/Delta pool (zero diagonal)
@@ -469,7 +469,7 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     const int G = b->n_graphs;
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[0], s));
     launch_degree(b->row_ptr, nullptr, b->n_nodes, w.deg, w.invd, s);
-    launch_row_table(b->row_ptr, b->col_idx, nullptr, b->node_off, 0, G, w.rows, w.col_r, nullptr, s);
+    launch_row_table(b->row_ptr, b->col_idx, nullptr, b->node_off, 0, G, b->n_nodes, w.rows, w.col_r, nullptr, s);
     hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, b->node_off, G, w.plan);
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[1], s));
 

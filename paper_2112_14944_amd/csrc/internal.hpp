@@ -15,7 +15,7 @@ void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int3
                  double* resid, RowEnt* rows, int32_t* col_r, float* w_r, int32_t* hist, float* ya, float* yb,
                  double* part, hipStream_t s);
 void launch_row_table(const int32_t* row_ptr, const int32_t* col_idx, const float* weight,
-                      const int64_t* node_off, int32_t n_single, int32_t blocks, RowEnt* table, int32_t* col_out,
-                      float* w_out, hipStream_t s);
+                      const int64_t* node_off, int32_t n_single, int32_t blocks, int64_t n_slots, RowEnt* table,
+                      int32_t* col_out, float* w_out, hipStream_t s);
 
 }  // namespace pprviz

@@ -27,22 +27,11 @@ __global__ void degree_kernel(const int32_t* __restrict__ row_ptr, const float* 
     invd[v] = (re > rs && d > 0.f) ? 1.0f / d : 1.0f;
 }
 
-// Row table of the resident tile (rows sorted by degree, longest first, ties
-// by row id; one block per graph), and a copy of the arcs with each row's arcs
-// dealt by LDS bank class.  In the tile, the four quads of a 16-lane LDS pass
-// read the rows of four consecutive slot positions, arc position m of each at
-// the same instruction, and a row u of a 16- (32-) column tile starts in bank
-// group u mod 4 (u mod 2).  Position m of the row in slot p therefore takes an
-// arc of class (m + p) mod 4 (mod 2) while that class lasts, so the four reads
-// of a pass fall in different bank groups.  Only the order of each row's arcs
-// changes (and with it the order of the FP32 sum).  The copy holds each
-// arc's LDS byte offset in the tile, (u - first node) * 4 COLS, not its node id.
+// Row table of the resident tile: rows sorted by degree, longest first, ties
+// by row id; one block per graph.
 __global__ __launch_bounds__(256) void row_table_kernel(const int32_t* __restrict__ row_ptr,
-                                                       const int32_t* __restrict__ col_idx,
-                                                       const float* __restrict__ weight,
                                                        const int64_t* __restrict__ node_off, int32_t n_single,
-                                                       RowEnt* __restrict__ table, int32_t* __restrict__ col_out,
-                                                       float* __restrict__ w_out) {
+                                                       RowEnt* __restrict__ table) {
     constexpr int kMaxRows = 4096;
     __shared__ uint32_t key[kMaxRows];
     const int g = blockIdx.x;
@@ -77,45 +66,78 @@ __global__ __launch_bounds__(256) void row_table_kernel(const int32_t* __restric
             __syncthreads();
         }
     }
+    for (int p = threadIdx.x; p < n; p += 256) {
+        const int v = (int)(key[p] & 4095u);
+        table[base + p] = RowEnt{row_ptr[base + v], row_ptr[base + v + 1], v, 0};
+    }
+}
+
+// Copy of the arcs for the resident tile, one thread per row slot of all
+// graphs, with each row's arcs dealt by LDS bank class.  In the tile, the four
+// quads of a 16-lane LDS pass read the rows of four consecutive slot
+// positions, arc position m of each at the same instruction, and a row u of a
+// 16- (32-) column tile starts in bank group u mod 4 (u mod 2).  Position m of
+// the row in slot p therefore takes an arc of class (m + p) mod 4 (mod 2)
+// while that class lasts, so the four reads of a pass fall in different bank
+// groups.  Only the order of each row's arcs changes (and with it the order of
+// the FP32 sum).  The copy holds each arc's LDS byte offset in the tile,
+// (u - first node) * 4 COLS, not its node id.
+__global__ __launch_bounds__(256) void bank_order_kernel(const int32_t* __restrict__ col_idx,
+                                                        const float* __restrict__ weight,
+                                                        const int64_t* __restrict__ node_off, int32_t n_graphs,
+                                                        int64_t n_slots, const RowEnt* __restrict__ table,
+                                                        int32_t* __restrict__ col_out, float* __restrict__ w_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_slots) return;
+    int g = 0;
+    if (node_off) {  // graph of slot i: largest g with node_off[g] <= i
+        int lo = 0, hi = n_graphs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (node_off[mid] <= i) lo = mid; else hi = mid - 1;
+        }
+        g = lo;
+    }
+    const int64_t base = node_off ? node_off[g] : 0;
+    const int n = node_off ? (int)(node_off[g + 1] - base) : (int)n_slots;
+    const int p = (int)(i - base);
     const int cols = res_cols_for(n);
     const int M = cols == 16 ? 4 : (cols == 32 ? 2 : 1);  // bank classes
     const int stride = (cols > 0 ? cols : 16) * 4;        // LDS bytes per row
-    for (int p = threadIdx.x; p < n; p += 256) {
-        const int v = (int)(key[p] & 4095u);
-        const int rs = row_ptr[base + v], re = row_ptr[base + v + 1];
-        table[base + p] = RowEnt{rs, re, v, 0};
-        if (M == 1) {
-            for (int e = rs; e < re; ++e) {
-                col_out[e] = (int)(col_idx[e] - base) * stride;
-                if (w_out) w_out[e] = weight[e];
-            }
-            continue;
+    const RowEnt r = table[i];
+    const int rs = r.rs, re = r.re;
+    if (M == 1) {
+        for (int e = rs; e < re; ++e) {
+            col_out[e] = (int)(col_idx[e] - base) * stride;
+            if (w_out) w_out[e] = weight[e];
         }
-        // next[c]: next arc of class c in the original order (re when none)
-        int next[4];
-        for (int c = 0; c < 4; ++c) {
-            int e = rs;
-            while (e < re && (int)((col_idx[e] - base) & (M - 1)) != c) ++e;
-            next[c] = c < M ? e : re;
-        }
-        for (int m = rs; m < re; ++m) {
-            int c = (m - rs + p) & (M - 1);
-            for (int t = 0; t < M && next[c] >= re; ++t) c = (c + 1) & (M - 1);
-            const int e = next[c];
-            col_out[m] = (int)(col_idx[e] - base) * stride;
-            if (w_out) w_out[m] = weight[e];
-            int f = e + 1;
-            while (f < re && (int)((col_idx[f] - base) & (M - 1)) != c) ++f;
-            next[c] = f;
-        }
+        return;
+    }
+    // next[c]: next arc of class c in the original order (re when none)
+    int next[4];
+    for (int c = 0; c < 4; ++c) {
+        int e = rs;
+        while (e < re && (int)((col_idx[e] - base) & (M - 1)) != c) ++e;
+        next[c] = c < M ? e : re;
+    }
+    for (int m = rs; m < re; ++m) {
+        int c = (m - rs + p) & (M - 1);
+        for (int t = 0; t < M && next[c] >= re; ++t) c = (c + 1) & (M - 1);
+        const int e = next[c];
+        col_out[m] = (int)(col_idx[e] - base) * stride;
+        if (w_out) w_out[m] = weight[e];
+        int f = e + 1;
+        while (f < re && (int)((col_idx[f] - base) & (M - 1)) != c) ++f;
+        next[c] = f;
     }
 }
 
 void launch_row_table(const int32_t* row_ptr, const int32_t* col_idx, const float* weight,
-                      const int64_t* node_off, int32_t n_single, int32_t blocks, RowEnt* table, int32_t* col_out,
-                      float* w_out, hipStream_t s) {
-    hipLaunchKernelGGL(row_table_kernel, dim3(blocks), dim3(256), 0, s, row_ptr, col_idx, weight, node_off,
-                       n_single, table, col_out, w_out);
+                      const int64_t* node_off, int32_t n_single, int32_t blocks, int64_t n_slots, RowEnt* table,
+                      int32_t* col_out, float* w_out, hipStream_t s) {
+    hipLaunchKernelGGL(row_table_kernel, dim3(blocks), dim3(256), 0, s, row_ptr, node_off, n_single, table);
+    hipLaunchKernelGGL(bank_order_kernel, dim3((unsigned)((n_slots + 255) / 256)), dim3(256), 0, s, col_idx, weight,
+                       node_off, blocks, n_slots, table, col_out, w_out);
 }
 
 template <int COLS, bool WEIGHTED>
@@ -179,7 +201,7 @@ void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int3
                  double* part, hipStream_t s) {
     const int n = g->n;
     if (use_resident(n)) {
-        launch_row_table(g->row_ptr, g->col_idx, g->weight, nullptr, n, 1, rows, col_r, g->weight ? w_r : nullptr, s);
+        launch_row_table(g->row_ptr, g->col_idx, g->weight, nullptr, n, 1, n, rows, col_r, g->weight ? w_r : nullptr, s);
         ResArgs a;
         a.rows = rows;
         a.row_ptr = g->row_ptr;
