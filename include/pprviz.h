@@ -104,6 +104,12 @@ size_t ppr_matrix_workspace(const ppr_csr* g, int32_t n_src, int32_t n_tgt);
  * Sources must be distinct valid node ids.  Precision: FP32 arithmetic,
  * FP64 for the residual check.  Returns PPR_ENOCONV (outputs still written)
  * when max_iter capped T before the tolerance was met.
+ * Kernel by size: n <= 2304 keeps a tile of sources in LDS; n <= 40831 keeps
+ * 4, 2 or 1 source columns of every node in LDS (these two never move the
+ * iterate through HBM); larger n streams the iterate through HBM.  On the
+ * middle path a row that lists more than n arcs (repeated neighbours) can
+ * exceed the workspace bound of its padded arc copy: the outputs and the
+ * residual are then NaN (PPR_ENONFINITE when resid_out is asked for).
  */
 ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src,
                       const int32_t* tgt, int32_t n_tgt, float alpha, double tol_l1,

@@ -11,7 +11,6 @@
 // The adjoint gathers over the same neighbours with the same coefficients as
 // the forward push, so it reuses the streaming step with a dense forcing term.
 #include "internal.hpp"
-#include "ppr_stream.hpp"
 
 namespace pprviz {
 
@@ -91,16 +90,8 @@ __global__ void edge_sum_kernel(const int32_t* __restrict__ row_ptr, const int32
 }
 
 struct BwdWs {
-    RowEnt* rows;
-    float* deg;
-    float* invd;
-    float* ya;
-    float* yb;
+    PprWs f;  // forward recompute (any kernel) plus the streaming buffers of the adjoint
     float* pi;
-    double* part;
-    int32_t* hist;
-    int32_t* col_r;  // recompute on the resident path: arcs in bank-class order
-    float* w_r;
     double* dq;
     double* dd;
     double* g;
@@ -108,20 +99,10 @@ struct BwdWs {
 };
 
 template <typename Cursor>
-static void bwd_layout(Cursor& c, int n, int64_t nnz, bool recompute, BwdWs* w) {
-    const int64_t ld = stream_ld(n);
+static void bwd_layout(Cursor& c, int n, int64_t nnz, bool weighted, bool recompute, BwdWs* w) {
     BwdWs t;
-    t.rows = c.template take<RowEnt>(n);
-    t.deg = c.template take<float>(n);
-    t.invd = c.template take<float>(n);
-    t.ya = c.template take<float>((size_t)n * ld);
-    t.yb = c.template take<float>((size_t)n * ld);
+    ppr_ws_layout(c, n, nnz, weighted, n, &t.f, true);
     t.pi = recompute ? c.template take<float>((size_t)n * n) : nullptr;
-    t.part = c.template take<double>((size_t)stream_resid_chunks(n) * ld);
-    t.hist = c.template take<int32_t>(kDegKeys);
-    const bool res = recompute && use_resident(n);
-    t.col_r = res ? c.template take<int32_t>((size_t)(nnz + kArcPad)) : nullptr;
-    t.w_r = res ? c.template take<float>((size_t)(nnz + kArcPad)) : nullptr;
     t.dq = c.template take<double>((size_t)std::max<int64_t>(nnz, 1));
     t.dd = c.template take<double>(n);
     t.g = c.template take<double>((size_t)std::max<int64_t>(nnz, 1));
@@ -138,7 +119,7 @@ extern "C" {
 size_t ppr_backward_workspace(const ppr_csr* g, int recompute) {
     if (g == nullptr || g->n < 1 || g->nnz < 0) return 0;
     WsSize c;
-    bwd_layout(c, g->n, g->nnz, recompute != 0, nullptr);
+    bwd_layout(c, g->n, g->nnz, g->weight != nullptr, recompute != 0, nullptr);
     return c.used;
 }
 
@@ -153,27 +134,27 @@ ppr_status ppr_matrix_backward(const ppr_csr* g, float alpha, int32_t T, const f
     const bool recompute = (ppr == nullptr);
     WsCursor cur{static_cast<char*>(ws), ws_bytes};
     BwdWs w;
-    bwd_layout(cur, g->n, g->nnz, recompute, &w);
+    bwd_layout(cur, g->n, g->nnz, g->weight != nullptr, recompute, &w);
     if (ws == nullptr || cur.used > ws_bytes) return PPR_EWORKSPACE;
     if (pending_error() != PPR_OK) return PPR_EHIP;
     if (g->nnz == 0) return PPR_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int n = g->n;
-    launch_degree(g->row_ptr, g->weight, n, w.deg, w.invd, s);
+    const PprWs& f = w.f;
+    launch_degree(g->row_ptr, g->weight, n, f.deg, f.invd, s);
     const float* pi = ppr;
     if (recompute) {
-        ppr_forward(g, nullptr, n, nullptr, n, alpha, T, w.pi, nullptr, w.deg, w.invd, nullptr, w.rows, w.col_r,
-                    w.w_r, w.hist, w.ya, w.yb, w.part, s);
+        ppr_forward(g, nullptr, n, nullptr, n, alpha, T, w.pi, nullptr, f.deg, f.invd, nullptr, f, s);
         pi = w.pi;
     }
-    stream_row_order(g->row_ptr, n, w.hist, w.rows, s);
+    stream_row_order(g->row_ptr, n, f.hist, f.rows, s);
     StreamArgs sa;
-    sa.rows = w.rows;
+    sa.rows = f.rows;
     sa.row_ptr = g->row_ptr;
     sa.col_idx = g->col_idx;
     sa.weight = g->weight;
-    sa.invd = w.invd;
-    sa.deg = w.deg;
+    sa.invd = f.invd;
+    sa.deg = f.deg;
     sa.n = n;
     sa.ncols = n;
     sa.ld = stream_ld(n);
@@ -181,12 +162,12 @@ ppr_status ppr_matrix_backward(const ppr_csr* g, float alpha, int32_t T, const f
     sa.src = nullptr;
     sa.forcing = grad_dppr;
     sa.ld_forcing = n;
-    const float* A = stream_power_iteration(sa, T, w.ya, w.yb, s);
+    const float* A = stream_power_iteration(sa, T, f.ya, f.yb, s);
     hipLaunchKernelGGL(row_of_arc_kernel, dim3((n + 255) / 256), dim3(256), 0, s, g->row_ptr, n, w.row_of_arc);
     hipLaunchKernelGGL(arc_dot_kernel, dim3((unsigned)((g->nnz + 3) / 4)), dim3(256), 0, s, w.row_of_arc, g->col_idx,
                        g->nnz, A, pi, n, w.dq);
     hipLaunchKernelGGL(row_dot_kernel, dim3((n + 3) / 4), dim3(256), 0, s, grad_dppr, pi, n, w.dd);
-    hipLaunchKernelGGL(arc_grad_kernel, dim3((n + 255) / 256), dim3(256), 0, s, g->row_ptr, g->weight, w.deg, w.dq,
+    hipLaunchKernelGGL(arc_grad_kernel, dim3((n + 255) / 256), dim3(256), 0, s, g->row_ptr, g->weight, f.deg, w.dq,
                        w.dd, n, alpha, w.g);
     hipLaunchKernelGGL(edge_sum_kernel, dim3((unsigned)((g->nnz + 255) / 256)), dim3(256), 0, s, g->row_ptr,
                        g->col_idx, w.row_of_arc, g->nnz, w.g, grad_arc);

@@ -1,10 +1,68 @@
-// Host-side functions shared between the library's translation units.
+// Host-side functions and workspace layouts shared between the library's
+// translation units.
 #pragma once
+
+#include <algorithm>
 
 #include "common.hpp"
 #include "ppr_core.hpp"
+#include "ppr_mid.hpp"
+#include "ppr_stream.hpp"
 
 namespace pprviz {
+
+// Workspace of the forward PPR (ppr_matrix, and the recompute inside
+// ppr_matrix_backward).  Only the buffers of the kernel that n selects are
+// taken, unless the streaming buffers are asked for as well.
+struct PprWs {
+    RowEnt* rows;
+    float* deg;
+    float* invd;
+    double* resid;
+    int32_t* col_r;  // resident tile: arcs in bank-class order
+    float* w_r;
+    MidWs mid;       // mid-size kernel: plan and arc stream
+    float* ya;       // streaming SpMM: iterate ping-pong
+    float* yb;
+    double* part;
+    int32_t* hist;
+};
+
+template <typename Cursor>
+void ppr_ws_layout(Cursor& c, int n, int64_t nnz, bool weighted, int n_src, PprWs* w, bool with_stream = false) {
+    PprWs t{};
+    t.rows = c.template take<RowEnt>(n);
+    t.deg = c.template take<float>(n);
+    t.invd = c.template take<float>(n);
+    t.resid = c.template take<double>(std::max(n_src, 1));
+    const bool res = res_cols_for(n) != 0;
+    const bool mid = mid_cols_for(n) != 0;
+    if (res) {
+        t.col_r = c.template take<int32_t>((size_t)(nnz + kArcPad));
+        t.w_r = weighted ? c.template take<float>((size_t)(nnz + kArcPad)) : nullptr;
+    }
+    if (mid) {
+        const int64_t groups = mid_stream_groups(n, nnz);
+        t.mid.rows = t.rows;
+        t.mid.hist = c.template take<int32_t>(kMidKeys);
+        t.mid.plan = c.template take<int32_t>(kPlanInts);
+        t.mid.slice_goff = c.template take<int32_t>((size_t)mid_slices(n));
+        t.mid.slice_slot = c.template take<int32_t>((size_t)mid_slices(n));
+        t.mid.vtab = c.template take<int2>((size_t)kMidWaves * kMidSlotCap * 64);
+        t.mid.sell = c.template take<uint16_t>((size_t)(groups * kMidGroup));
+        t.mid.sellw = weighted ? c.template take<float>((size_t)(groups * kMidGroup)) : nullptr;
+        t.mid.tmp_u = c.template take<int32_t>((size_t)std::max<int64_t>(nnz, 1));
+        t.mid.tmp_w = weighted ? c.template take<float>((size_t)std::max<int64_t>(nnz, 1)) : nullptr;
+    }
+    if ((!res && !mid) || with_stream) {
+        const int64_t ldy = stream_ld(with_stream ? n : n_src);
+        t.ya = c.template take<float>((size_t)n * ldy);
+        t.yb = c.template take<float>((size_t)n * ldy);
+        t.part = c.template take<double>((size_t)stream_resid_chunks(n) * ldy);
+        t.hist = c.template take<int32_t>(kDegKeys);
+    }
+    if (w) *w = t;
+}
 
 ppr_status validate_csr(const ppr_csr* g);
 bool use_resident(int n);
@@ -12,8 +70,7 @@ void launch_degree(const int32_t* row_ptr, const float* weight, int64_t n, float
                    hipStream_t s);
 void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int32_t* tgt, int32_t n_tgt,
                  float alpha, int32_t T, float* ppr_out, float* dppr_out, const float* deg, const float* invd,
-                 double* resid, RowEnt* rows, int32_t* col_r, float* w_r, int32_t* hist, float* ya, float* yb,
-                 double* part, hipStream_t s);
+                 double* resid, const PprWs& w, hipStream_t s);
 void launch_row_table(const int32_t* row_ptr, const int32_t* col_idx, const float* weight,
                       const int64_t* node_off, int32_t n_single, int32_t blocks, int64_t n_slots, RowEnt* table,
                       int32_t* col_out, float* w_out, hipStream_t s);

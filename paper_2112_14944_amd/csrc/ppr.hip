@@ -5,7 +5,6 @@
 #include <algorithm>
 
 #include "ppr_core.hpp"
-#include "ppr_stream.hpp"
 #include "internal.hpp"
 
 namespace pprviz {
@@ -170,20 +169,6 @@ static void launch_resident(bool weighted, const ResArgs& a, int n, int n_src, i
         hipLaunchKernelGGL((ppr_resident_kernel<COLS, false>), grid, dim3(kResThreads), 0, s, a, n, n_src, n_tgt);
 }
 
-// Workspace layout of ppr_matrix.
-struct PprWs {
-    RowEnt* rows;
-    float* deg;
-    float* invd;
-    double* resid;
-    float* ya;
-    float* yb;
-    double* part;
-    int32_t* hist;
-    int32_t* col_r;  // resident path: arcs in bank-class order
-    float* w_r;
-};
-
 ppr_status validate_csr(const ppr_csr* g) {
     if (g == nullptr || g->n < 1 || g->nnz < 0 || g->nnz >= (int64_t)INT32_MAX) return PPR_EINVAL;
     if (g->row_ptr == nullptr || (g->nnz > 0 && g->col_idx == nullptr)) return PPR_EINVAL;
@@ -192,21 +177,22 @@ ppr_status validate_csr(const ppr_csr* g) {
 
 bool use_resident(int n) { return res_cols_for(n) != 0; }
 
-// T pushes from every source; deg/invd must already hold the degrees.  The
-// stream-path buffers (ya, yb, part) are only touched when n is too large for
-// the LDS-resident kernel.
+// T pushes from every source; deg/invd must already hold the degrees.  Three
+// kernels by size: the LDS-resident tile (n <= 2304), the mid-size kernel
+// with the iterate columns in LDS (n <= 40831), and the streaming SpMM with
+// the iterate in HBM.
 void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int32_t* tgt, int32_t n_tgt,
                  float alpha, int32_t T, float* ppr_out, float* dppr_out, const float* deg, const float* invd,
-                 double* resid, RowEnt* rows, int32_t* col_r, float* w_r, int32_t* hist, float* ya, float* yb,
-                 double* part, hipStream_t s) {
+                 double* resid, const PprWs& w, hipStream_t s) {
     const int n = g->n;
     if (use_resident(n)) {
-        launch_row_table(g->row_ptr, g->col_idx, g->weight, nullptr, n, 1, n, rows, col_r, g->weight ? w_r : nullptr, s);
+        launch_row_table(g->row_ptr, g->col_idx, g->weight, nullptr, n, 1, n, w.rows, w.col_r,
+                         g->weight ? w.w_r : nullptr, s);
         ResArgs a;
-        a.rows = rows;
+        a.rows = w.rows;
         a.row_ptr = g->row_ptr;
-        a.col_idx = col_r;
-        a.weight = g->weight ? w_r : nullptr;
+        a.col_idx = w.col_r;
+        a.weight = g->weight ? w.w_r : nullptr;
         a.invd = invd;
         a.deg = deg;
         a.src = src;
@@ -222,10 +208,12 @@ void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int3
             case 32: launch_resident<32>(wt, a, n, n_src, n_tgt, s); break;
             default: launch_resident<16>(wt, a, n, n_src, n_tgt, s); break;
         }
+    } else if (mid_cols_for(n) != 0) {
+        mid_forward(g, src, n_src, tgt, n_tgt, alpha, T, ppr_out, dppr_out, deg, invd, resid, w.mid, s);
     } else {
-        stream_row_order(g->row_ptr, n, hist, rows, s);
+        stream_row_order(g->row_ptr, n, w.hist, w.rows, s);
         StreamArgs sa;
-        sa.rows = rows;
+        sa.rows = w.rows;
         sa.row_ptr = g->row_ptr;
         sa.col_idx = g->col_idx;
         sa.weight = g->weight;
@@ -238,49 +226,9 @@ void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int3
         sa.src = src;
         sa.forcing = nullptr;
         sa.ld_forcing = 0;
-        const float* x = stream_power_iteration(sa, T, ya, yb, s);
+        const float* x = stream_power_iteration(sa, T, w.ya, w.yb, s);
         stream_write_outputs(x, sa, tgt, n_tgt, ppr_out, dppr_out, s);
-        if (resid) stream_residuals(x, sa, part, resid, s);
-    }
-}
-
-template <typename Cursor>
-static void ppr_ws_layout(Cursor& c, int n, int64_t nnz, bool weighted, int n_src, PprWs* w) {
-    auto* rows = c.template take<RowEnt>(n);
-    auto* deg = c.template take<float>(n);
-    auto* invd = c.template take<float>(n);
-    auto* resid = c.template take<double>(std::max(n_src, 1));
-    if (w) {
-        w->rows = rows;
-        w->deg = deg;
-        w->invd = invd;
-        w->resid = resid;
-        w->ya = w->yb = nullptr;
-        w->part = nullptr;
-        w->hist = nullptr;
-        w->col_r = nullptr;
-        w->w_r = nullptr;
-    }
-    if (use_resident(n)) {
-        auto* col_r = c.template take<int32_t>((size_t)(nnz + kArcPad));
-        auto* w_r = weighted ? c.template take<float>((size_t)(nnz + kArcPad)) : nullptr;
-        if (w) {
-            w->col_r = col_r;
-            w->w_r = w_r;
-        }
-    }
-    if (!use_resident(n)) {
-        const int64_t ldy = stream_ld(n_src);
-        auto* ya = c.template take<float>((size_t)n * ldy);
-        auto* yb = c.template take<float>((size_t)n * ldy);
-        auto* part = c.template take<double>((size_t)stream_resid_chunks(n) * ldy);
-        auto* hist = c.template take<int32_t>(kDegKeys);
-        if (w) {
-            w->ya = ya;
-            w->yb = yb;
-            w->part = part;
-            w->hist = hist;
-        }
+        if (resid) stream_residuals(x, sa, w.part, resid, s);
     }
 }
 
@@ -353,7 +301,7 @@ ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src, const
     if (tgt == nullptr && n_tgt != g->n) return PPR_EINVAL;
     if (!(alpha > 0.0f && alpha < 1.0f) || max_iter < 0) return PPR_EINVAL;
     if ((int64_t)n_src * (int64_t)std::max(n_tgt, 1) > ((int64_t)1 << 40)) return PPR_EUNSUPPORTED;
-    if (!use_resident(g->n) && g->n > kStreamMaxN) return PPR_EUNSUPPORTED;
+    if (g->n > kStreamMaxN) return PPR_EUNSUPPORTED;
     int32_t T = 0, conv = 1;
     st = pprviz_pushes_for_tolerance(alpha, tol_l1, max_iter, &T, &conv);
     if (st != PPR_OK) return st;
@@ -368,8 +316,7 @@ ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src, const
     const int n = g->n;
     launch_degree(g->row_ptr, g->weight, n, w.deg, w.invd, s);
 
-    ppr_forward(g, src, n_src, tgt, n_tgt, alpha, T, ppr_out, dppr_out, w.deg, w.invd, w.resid, w.rows, w.col_r,
-                w.w_r, w.hist, w.ya, w.yb, w.part, s);
+    ppr_forward(g, src, n_src, tgt, n_tgt, alpha, T, ppr_out, dppr_out, w.deg, w.invd, w.resid, w, s);
     st = launch_status();
     if (st != PPR_OK) return st;
     if (resid_out) {

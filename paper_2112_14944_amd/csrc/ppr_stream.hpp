@@ -1,8 +1,8 @@
-// Power iteration for graphs too large for the LDS-resident tile kernel: the
-// node-major iterate lives in HBM (ping-pong buffers) and each push is one
-// launch.  A wave owns one row per pass and its 64 lanes are 64 consecutive
-// source columns, so every gathered neighbour row is one contiguous 256-byte
-// read and the arc list is wave-uniform (scalar loads).
+// Power iteration for graphs too large to keep any source column of the
+// iterate in LDS (more than 40831 nodes): the iterate lives in HBM (ping-pong
+// buffers, column slabs of 32 sources) and each push is one launch.  A wave
+// takes 8 rows side by side, so every gathered neighbour row is one
+// contiguous 128-byte read (details at stream_step_kernel).
 //
 // The same step serves the adjoint solve of the weight gradient:
 //     A_{k+1} = Gb + (1-alpha) P^T A_k      (Gb = D G, forcing term)
@@ -83,56 +83,64 @@ __device__ __forceinline__ void stream_block_map(const StreamGrid& g, int& slab,
     }
 }
 
-// Row order for the streaming step: a counting sort of the rows by degree,
-// largest first, so the 8 rows a wave takes side by side have (nearly) equal
-// arc counts.  The order within a degree class is whatever the atomics give;
-// it only decides which rows share a wave, never a sum.
+// Row order by degree, largest first: a counting sort over KEYS degree
+// classes (degrees from KEYS - 1 up share the first class), so that the 8
+// rows a streaming-step wave takes side by side have (nearly) equal arc
+// counts.  The order within a class is whatever the atomics give; it only
+// decides which rows share a wave, never a sum.  (The mid-size kernel reuses
+// the histogram and scan with exact classes and a stable scatter of its own.)
+template <int KEYS>
 static __global__ void stream_deg_hist_kernel(const int32_t* __restrict__ row_ptr, int32_t n,
                                               int32_t* __restrict__ hist) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    const int d = min(row_ptr[v + 1] - row_ptr[v], kDegKeys - 1);
-    atomicAdd(&hist[kDegKeys - 1 - d], 1);
+    const int d = min(row_ptr[v + 1] - row_ptr[v], KEYS - 1);
+    atomicAdd(&hist[KEYS - 1 - d], 1);
 }
 
-// Exclusive prefix sum of the kDegKeys class counts, in place (one block).
-static __global__ __launch_bounds__(256) void stream_deg_scan_kernel(int32_t* __restrict__ hist) {
-    constexpr int kPer = kDegKeys / 256;
-    __shared__ int32_t part[256];
-    int32_t loc[kPer];
+// Exclusive prefix sum of the KEYS class counts, in place (one block).
+template <int KEYS>
+static __global__ __launch_bounds__(1024) void stream_deg_scan_kernel(int32_t* __restrict__ hist) {
+    constexpr int kPer = KEYS / 1024;
+    static_assert(KEYS % 1024 == 0, "keys");
+    __shared__ int32_t part[1024];
+    const int t0 = threadIdx.x * kPer;
     int32_t t = 0;
-    for (int i = 0; i < kPer; ++i) {
-        loc[i] = t;
-        t += hist[threadIdx.x * kPer + i];
-    }
+    for (int i = 0; i < kPer; ++i) t += hist[t0 + i];
     part[threadIdx.x] = t;
     __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
+    for (int o = 1; o < 1024; o <<= 1) {
         const int32_t x = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
         __syncthreads();
         part[threadIdx.x] += x;
         __syncthreads();
     }
-    const int32_t base = part[threadIdx.x] - t;
-    for (int i = 0; i < kPer; ++i) hist[threadIdx.x * kPer + i] = base + loc[i];
+    int32_t run = part[threadIdx.x] - t;
+    for (int i = 0; i < kPer; ++i) {
+        const int32_t h = hist[t0 + i];
+        hist[t0 + i] = run;
+        run += h;
+    }
 }
 
+template <int KEYS>
 static __global__ void stream_deg_scatter_kernel(const int32_t* __restrict__ row_ptr, int32_t n,
                                                  int32_t* __restrict__ cursor, RowEnt* __restrict__ rows) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const int rs = row_ptr[v], re = row_ptr[v + 1];
-    const int d = min(re - rs, kDegKeys - 1);
-    const int pos = atomicAdd(&cursor[kDegKeys - 1 - d], 1);
+    const int d = min(re - rs, KEYS - 1);
+    const int pos = atomicAdd(&cursor[KEYS - 1 - d], 1);
     rows[pos] = RowEnt{rs, re, (int32_t)v, 0};
 }
 
+template <int KEYS = kDegKeys>
 inline void stream_row_order(const int32_t* row_ptr, int32_t n, int32_t* hist, RowEnt* rows, hipStream_t s) {
-    fill<int32_t>(hist, 0, kDegKeys, s);
+    fill<int32_t>(hist, 0, KEYS, s);
     const unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(stream_deg_hist_kernel, dim3(blocks), dim3(256), 0, s, row_ptr, n, hist);
-    hipLaunchKernelGGL(stream_deg_scan_kernel, dim3(1), dim3(256), 0, s, hist);
-    hipLaunchKernelGGL(stream_deg_scatter_kernel, dim3(blocks), dim3(256), 0, s, row_ptr, n, hist, rows);
+    hipLaunchKernelGGL(stream_deg_hist_kernel<KEYS>, dim3(blocks), dim3(256), 0, s, row_ptr, n, hist);
+    hipLaunchKernelGGL(stream_deg_scan_kernel<KEYS>, dim3(1), dim3(1024), 0, s, hist);
+    hipLaunchKernelGGL(stream_deg_scatter_kernel<KEYS>, dim3(blocks), dim3(256), 0, s, row_ptr, n, hist, rows);
 }
 
 __device__ __forceinline__ void f4_acc(float4& a, float4 y) {

@@ -111,11 +111,18 @@ def test_batch_validation_and_limits(lib):
 
 def test_workspace_queries_grow_with_size(lib):
     small = L.ppr_csr(500, 4000, None, None, None)
-    large = L.ppr_csr(20000, 400000, None, None, None)
+    mid = L.ppr_csr(20000, 400000, None, None, None)
+    large = L.ppr_csr(50000, 1000000, None, None, None)
     assert 0 < lib.ppr_matrix_workspace(C.byref(small), 500, 500) < (1 << 20)
+    # the mid-size kernel keeps the iterate in LDS: its workspace is the
+    # padded 16-bit arc copy (bounded by 64 n + nnz entries plus a group per
+    # slice) and small tables, independent of the source count
+    ws_mid = lib.ppr_matrix_workspace(C.byref(mid), 20000, 20000)
+    assert 2 * (64 * 20000 + 400000) <= ws_mid < (16 << 20)
+    assert ws_mid - lib.ppr_matrix_workspace(C.byref(mid), 2, 2) <= 8 * 20000 + 512  # FP64 residual per source
     # the streaming path holds two node-major iterates of n x round64(S) floats
     ws = lib.ppr_matrix_workspace(C.byref(large), 20000, 20000)
-    assert ws >= 2 * 20000 * 20032 * 4
+    assert ws >= 2 * 50000 * 20032 * 4
     assert lib.layout_workspace(20000) >= 8 * math.ceil(20000 / 16)
     assert lib.ppr_backward_workspace(C.byref(large), 1) > lib.ppr_backward_workspace(C.byref(large), 0)
 

@@ -50,11 +50,15 @@ def test_c1_erdos_renyi_all_pairs(ops):
     assert s_gpu < O.stress(X0, D_o)
 
 
-def test_weighted_isolated_subsets(ops):
+@pytest.mark.parametrize("n", [300, 5000, 12000, 25000])
+def test_weighted_isolated_subsets(ops, n):
     # weighted SBM with an isolated node, a ragged source subset, a shuffled
-    # target subset, fixed T (tol <= 0)
-    n = 300
-    g0 = synth.sbm(synth.equal_blocks(n, 5), 0.12, 0.01, 77, weighted=(0.5, 2.0, 78))
+    # target subset, fixed T (tol <= 0); n = 300 runs the resident tile, the
+    # others the mid-size kernel at 4, 2 and 1 columns per block
+    blocks = 5 if n == 300 else 16
+    p_in = 0.12 if n == 300 else 12.0 / (n / blocks)
+    p_out = 0.01 if n == 300 else 2.0 / n
+    g0 = synth.sbm(synth.equal_blocks(n, blocks), p_in, p_out, 77 + n, weighted=(0.5, 2.0, 78))
     keep = (g0.eu != 7) & (g0.ev != 7)
     g = synth.build_graph(n, g0.eu[keep], g0.ev[keep], g0.weight[keep])
     rng = np.random.default_rng(5)
@@ -64,6 +68,7 @@ def test_weighted_isolated_subsets(ops):
     tgt = rng.permutation(n)
     tgt = np.concatenate([[7], tgt[tgt != 7]])[:123]  # shuffled, holds the isolated node
     tgt = np.roll(tgt, 40)
+    print(f"[weighted] n={n} nnz={g.nnz} sources={len(src)}", flush=True)
     ppr, dppr, T, resid = ops.ppr_matrix(_csr(ops, g), src, tgt=tgt, tol=0.0, max_iter=60, check_residual=True)
     est, dppr_o, T_o, res_o, d = oracle_ppr(g, src, T=60)
     assert T == 60
@@ -74,17 +79,37 @@ def test_weighted_isolated_subsets(ops):
     assert abs(ppr[i7].cpu().numpy()[tgt == 7].item() - (1 - (1 - ALPHA) ** 60)) <= 1e-6
 
 
-@pytest.mark.parametrize("n", [576, 577, 1152, 1153, 2304, 2305, 3001])
-def test_tile_width_boundaries_and_stream_path(ops, n):
-    # 64/32/16-column resident tiles switch at 576/1152/2304; above 2304 the
-    # iterate streams through HBM.
+@pytest.mark.parametrize("n", [576, 577, 1152, 1153, 2304, 2305, 3001, 10207, 10208, 20415, 20416, 40831, 40832])
+def test_kernel_size_boundaries(ops, n):
+    # 64/32/16-column resident tiles switch at 576/1152/2304; the mid-size
+    # kernel keeps 4/2/1 columns of every node in LDS up to 10207/20415/40831;
+    # above that the iterate streams through HBM.
     g = synth.erdos_renyi(n, 10, 1000 + n)
     src = synth.random_sources(g, 70, 2000 + n)
+    print(f"[sizes] n={n} nnz={g.nnz}", flush=True)
     ppr, dppr, T, resid = ops.ppr_matrix(_csr(ops, g), src, tol=1e-6, check_residual=True)
     est, dppr_o, T_o, res_o, d = oracle_ppr(g, src, tol=1e-6)
     assert T == T_o == 86
     assert_ppr_close(ppr, dppr, est, dppr_o, d[src])
     assert np.abs(resid - res_o).max() <= 2e-6
+
+
+def test_mid_repeated_arcs_flagged(ops):
+    # a row listing one neighbour far more than n times breaks the mid-size
+    # kernel's bound on its padded arc copy: NaN outputs, ENONFINITE
+    n = 2400
+    reps = 50000
+    row_ptr = np.zeros(n + 1, dtype=np.int32)
+    row_ptr[1] = reps
+    row_ptr[2:] = 2 * reps
+    col = np.concatenate([np.full(reps, 1), np.full(reps, 0)]).astype(np.int32)
+    csr = ops.Csr(n, len(col), torch.as_tensor(row_ptr, device="cuda"), torch.as_tensor(col, device="cuda"), None)
+    from paper_2112_14944_amd._lib import PPR_ENONFINITE, PprvizError
+    with pytest.raises(PprvizError) as ei:
+        ops.ppr_matrix(csr, [0, 5], tol=1e-6, check_residual=True)
+    assert ei.value.status == PPR_ENONFINITE
+    ppr, _, _, _ = ops.ppr_matrix(csr, [0, 5], tol=1e-6)
+    assert torch.isnan(ppr).all().item()
 
 
 def test_degenerate_cases(ops):
