@@ -34,6 +34,7 @@ constexpr int kMidSlotCap = 48;       // slot table stride per wave (largest KS)
 constexpr int kMidGroup = 256;        // stream entries per group: 64 lanes x 4 arcs
 constexpr int kMidPrefetch = 2;       // groups each lane reads ahead
 constexpr int kMidKeys = 65536;       // exact degree classes of the row order
+constexpr int kMidMaxParts = 1024;    // parts of split rows: they fill at most the first 16 slices
 
 // Columns per block for an n-node graph (0: not a mid-size graph).
 __host__ __device__ inline int mid_cols_for(int n) {
@@ -52,20 +53,108 @@ __host__ __device__ inline int64_t mid_slices(int n) { return (n + 63) / 64; }
 
 // Bound on the stream's groups.  With rows sorted by degree, slice i >= 1 is
 // no wider than the smallest row of slice i-1, so 64 * width(i) is at most
-// the arc count of slice i-1; slice 0 adds at most 64 * (largest degree), and
-// rounding up to whole groups at most 256 entries per slice.  The largest
+// the arc count of slice i-1; the first slice adds at most 64 * (largest
+// degree), and rounding up to whole groups at most 256 entries per slice.  The largest
 // degree is at most n when no row lists a neighbour twice; a graph that breaks
 // the bound is flagged by the plan and gets NaN outputs.
+// The parts of split rows (below) fill at most 16 slices, each at most as
+// wide as the largest degree.
 inline int64_t mid_stream_groups(int n, int64_t nnz) {
     const int64_t maxdeg = nnz < (int64_t)n ? nnz : (int64_t)n;
-    return (64 * maxdeg + nnz + kMidGroup * mid_slices(n) + kMidGroup - 1) / kMidGroup + kMidPrefetch;
+    return (64 * 17 * (maxdeg + 4) + nnz + kMidGroup * mid_slices(n + kMidMaxParts) + kMidGroup - 1) / kMidGroup +
+           kMidPrefetch;
 }
 
 // Plan (int32 words): group counts of each wave's slots, the first group of
-// each wave's stream, and the overflow flag.
+// each wave's stream, the overflow flag, the row count after splitting and
+// the number of split rows.
 constexpr int kPlanStart = kMidWaves * kMidSlotCap;
 constexpr int kPlanFlag = kPlanStart + kMidWaves;
-constexpr int kPlanInts = kPlanFlag + 1;
+constexpr int kPlanRows = kPlanFlag + 1;
+constexpr int kPlanHubs = kPlanRows + 1;
+constexpr int kPlanInts = kPlanHubs + 1;
+
+// Split of long rows.  One push costs a block as long as its busiest wave
+// takes, and a wave holding the slice of the longest rows can take far longer
+// than the mean when a few rows have hundreds of arcs.  Rows longer than D
+// arcs are therefore cut into parts of D arcs (the last part shorter), each
+// part a row of its own, placed ahead of all other rows so that they fill
+// the first (at most 16) slices, which the deal below gives to slot 0 of
+// waves 0..15.  After slot 0, a part's lane writes its sum to a partial slot
+// in LDS just past the iterate; after the push's barrier, one lane per split
+// row adds the partials in part order (a fixed order) in FP64, so that a row
+// of thousands of arcs is summed no less accurately than a short one, and
+// writes the row.  D
+// starts at half a wave's mean share of the arcs and doubles until the parts
+// fit the spare LDS after the iterate and the first 16 slices; nothing is
+// split when the longest row fits in a wave's mean share.
+
+// One block.  Chooses D, writes the row list after splitting (parts first,
+// tagged with their partial index + 1), one combine entry per split row
+// (LDS byte address of the row, scale, LDS byte address of its first
+// partial, part count), and clears the slot-0 partial targets.
+static __global__ __launch_bounds__(1024) void mid_split_kernel(const RowEnt* __restrict__ rows, int32_t n,
+                                                               int64_t nnz, int32_t C, float alpha,
+                                                               const float* __restrict__ invd,
+                                                               int32_t* __restrict__ plan, RowEnt* __restrict__ vrows,
+                                                               int4* __restrict__ comb,
+                                                               int32_t* __restrict__ part_dst) {
+    __shared__ int32_t hub_pb[kMidMaxParts];
+    __shared__ int64_t sD;
+    __shared__ int32_t sH, sP;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        // target part length: half a wave's mean share of the arcs (16 waves)
+        const int64_t groups = (nnz * 11 / 10 + kMidGroup - 1) / kMidGroup;
+        int64_t D = 4 * max((int64_t)2, (groups + 2 * kMidWaves - 1) / (2 * kMidWaves));
+        // no split when the widest slice is no wider than a wave's mean share:
+        // the deal already balances such slices
+        const int64_t maxdeg = rows[0].re - rows[0].rs;
+        if ((maxdeg + 3) / 4 <= groups / kMidWaves) D = INT64_MAX / 4;
+        const int cap = min(kMidMaxParts, (kMidLdsFloats - (n + 1) * C) / C);
+        int H = 0, P = 0;
+        for (;;) {
+            H = 0;
+            P = 0;
+            while (H < n && (int64_t)(rows[H].re - rows[H].rs) > D && P <= cap) {
+                P += (int)(((int64_t)(rows[H].re - rows[H].rs) + D - 1) / D);
+                ++H;
+            }
+            if (P <= cap && (H == n || (int64_t)(rows[H].re - rows[H].rs) <= D)) break;
+            D *= 2;
+        }
+        int pb = 0;
+        for (int h = 0; h < H; ++h) {
+            hub_pb[h] = pb;
+            pb += (int)(((int64_t)(rows[h].re - rows[h].rs) + D - 1) / D);
+        }
+        sD = D;
+        sH = H;
+        sP = P;
+        plan[kPlanRows] = P + n - H;
+        plan[kPlanHubs] = H;
+    }
+    __syncthreads();
+    const int64_t D = sD;
+    const int H = sH, P = sP;
+    const int part0 = (n + 1) * C * 4;  // LDS byte address of partial slot 0
+    for (int h = tid; h < H; h += 1024) {
+        const RowEnt e = rows[h];
+        const int m = (int)(((int64_t)(e.re - e.rs) + D - 1) / D);
+        const int pb = hub_pb[h];
+        for (int j = 0; j < m; ++j) {
+            const int a = e.rs + (int)(j * D);
+            const int b = (int)min((int64_t)e.re, (int64_t)e.rs + (j + 1) * D);
+            vrows[pb + j] = RowEnt{a, b, e.v, pb + j + 1};
+        }
+        comb[h] = make_int4(e.v * C * 4, __float_as_int((1.0f - alpha) * invd[e.v]), part0 + pb * C * 4, m);
+    }
+    for (int i = H + tid; i < n; i += 1024) {
+        const RowEnt e = rows[i];
+        vrows[P + i - H] = RowEnt{e.rs, e.re, e.v, 0};
+    }
+    for (int i = tid; i < kMidWaves * kWave; i += 1024) part_dst[i] = -1;
+}
 
 // Stable scatter of the rows into degree order (one block): rows go in
 // chunks of 1024 ids; each chunk is sorted by (class, id) in LDS, and a row's
@@ -129,10 +218,12 @@ static __global__ __launch_bounds__(1024) void mid_row_order_kernel(const int32_
     }
 }
 
-// One block.  Slice widths (in groups), then the longest-first deal of the
-// slices to waves (wave 0; lanes 0..15 hold the waves' loads and slot
-// counts), then the stream offsets.
-static __global__ __launch_bounds__(1024) void mid_plan_kernel(const RowEnt* __restrict__ rows, int32_t n,
+// One block, over the rows after splitting.  Slice widths (in groups), then
+// the longest-first deal of the slices to waves (wave 0; lanes 0..15 hold the
+// waves' loads and slot counts; slices 0..15 go to slot 0 of waves 0..15,
+// as all loads start at 0 and ties go to the lowest wave), then the stream
+// offsets.
+static __global__ __launch_bounds__(1024) void mid_plan_kernel(const RowEnt* __restrict__ rows,
                                                               int32_t ks, int64_t cap_groups,
                                                               int32_t* __restrict__ plan,
                                                               int32_t* __restrict__ slice_goff,
@@ -143,6 +234,7 @@ static __global__ __launch_bounds__(1024) void mid_plan_kernel(const RowEnt* __r
     __shared__ int32_t cnt[kMidWaves];
     __shared__ int32_t flag;
     const int tid = threadIdx.x;
+    const int n = plan[kPlanRows];  // rows after splitting
     const int nsl = (n + 63) / 64;
     for (int i = tid; i < kSlots; i += 1024) slot_slice[i] = -1;
     for (int i = tid; i < nsl; i += 1024) {
@@ -196,10 +288,11 @@ static __global__ __launch_bounds__(1024) void mid_plan_kernel(const RowEnt* __r
     }
 }
 
-// One wave per slice: the arc stream of its 64 rows, as LDS float indices
+// One wave per LDS pass of a slice (C waves per slice, M = 64 / C rows
+// each): the arc stream of its rows, as LDS float indices
 // u * C (weights alongside), padded with the zero row n * C; a row without
 // arcs gets one arc to itself of weight 1 (the implicit self-loop).  Also the
-// rows' nodes and scales (1-alpha)/d in their slot's table.
+// rows' LDS byte addresses (u * 4 C) and scales (1-alpha)/d in their slot's table.
 //
 // Arcs are dealt to stream positions by LDS bank class.  Row u of the tile
 // starts at bank (u * C) mod 64, so its class is u mod M, M = 64 / C, and one
@@ -215,24 +308,31 @@ static __global__ __launch_bounds__(64) void mid_fill_kernel(
     const RowEnt* __restrict__ rows, const int32_t* __restrict__ col_idx, const float* __restrict__ weight,
     const float* __restrict__ invd, int32_t n, int32_t C, float alpha, const int32_t* __restrict__ plan,
     const int32_t* __restrict__ slice_goff, const int32_t* __restrict__ slice_slot, int32_t* __restrict__ tmp_u,
-    float* __restrict__ tmp_w, uint16_t* __restrict__ sell, float* __restrict__ sellw, int2* __restrict__ vtab) {
+    float* __restrict__ tmp_w, uint16_t* __restrict__ sell, float* __restrict__ sellw, int2* __restrict__ vtab,
+    int32_t* __restrict__ part_dst) {
     __shared__ int32_t beg[kWave][kWave];  // per lane and class: first bucketed arc
     __shared__ int32_t pos[kWave][kWave];  // per lane and class: one past the last remaining arc
     const int lane = threadIdx.x;
-    const int64_t sl = blockIdx.x;
     if (plan[kPlanFlag] != 0) return;
+    const int nv = plan[kPlanRows];  // rows after splitting
     const int M = kWave / C;
+    const int passes = kWave / M;
+    const int64_t sl = blockIdx.x / passes;
+    if (sl >= mid_slices(nv)) return;
+    const int q0 = (int)(blockIdx.x % passes) * M;  // first slice lane of this pass
+    const int q = q0 + lane;                         // this lane's position in the slice
     const uint64_t full = M == 64 ? ~0ull : ((1ull << M) - 1);
     const int slot = slice_slot[sl];
     const int64_t goff = slice_goff[sl];
     const int W = 4 * plan[slot];
-    const int64_t i = sl * 64 + lane;
-    int v = -1, rs = 0, re = 0;
-    if (i < n) {
+    const int64_t i = sl * 64 + q;
+    int v = -1, rs = 0, re = 0, tag = 0;
+    if (lane < M && i < nv) {
         const RowEnt e = rows[i];
         v = e.v;
         rs = e.rs;
         re = e.re;
+        tag = e.pad;
     }
     const bool self = v >= 0 && re == rs;
     // bucket the row's arcs by class
@@ -258,8 +358,8 @@ static __global__ __launch_bounds__(64) void mid_fill_kernel(
     if (self) avail = 1ull << (v & (M - 1));
     const int zc = n & (M - 1);
     const uint32_t zero = (uint32_t)n * (uint32_t)C;
-    uint2* d = reinterpret_cast<uint2*>(sell) + goff * 64 + lane;
-    float4* dw = sellw ? reinterpret_cast<float4*>(sellw) + goff * 64 + lane : nullptr;
+    uint2* d = reinterpret_cast<uint2*>(sell) + goff * 64 + q;
+    float4* dw = sellw ? reinterpret_cast<float4*>(sellw) + goff * 64 + q : nullptr;
     uint32_t pk[4];
     float pw[4];
     // the deal runs on the scalar unit: every value below except my_c and
@@ -273,19 +373,19 @@ static __global__ __launch_bounds__(64) void mid_fill_kernel(
         int my_c = -1;
         const uint64_t live = __ballot(avail != 0);  // lanes with arcs left
         const int rot = k & Mm1;
-        for (int p = 0; p < kWave; p += Mm1 + 1) {
+        {
             uint64_t z = fullS, o = 0, t = 0;
-            const uint64_t pm = (live >> p) & fullS;
+            const uint64_t pm = live & fullS;
             if (pm != fullS) {  // some lane of the pass reads the zero row
                 z &= ~(1ull << zcS);
                 o |= 1ull << zcS;
             }
-            // the pass's lanes with arcs left, in turn from lane p + rot
+            // the pass's lanes with arcs left, in turn from lane rot
             uint64_t rest = rot == 0 ? pm : (((pm >> rot) | (pm << (Mm1 + 1 - rot))) & fullS);
             while (rest != 0) {
                 const int b = __builtin_ctzll(rest);
                 rest &= rest - 1;
-                const int L = __builtin_amdgcn_readfirstlane(p + ((b + rot) & Mm1));
+                const int L = __builtin_amdgcn_readfirstlane((b + rot) & Mm1);
                 const uint64_t a =
                     ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(avail >> 32), L) << 32) |
                     (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)avail, L);
@@ -293,7 +393,7 @@ static __global__ __launch_bounds__(64) void mid_fill_kernel(
                 if (m == 0) m = a & o;
                 if (m == 0) m = a & t;
                 if (m == 0) m = a;
-                const int sh = (7 * L + 3 * k) & Mm1;
+                const int sh = (7 * (q0 + L) + 3 * k) & Mm1;
                 const uint64_t r = sh == 0 ? m : (((m >> sh) | (m << (Mm1 + 1 - sh))) & fullS);
                 const int c = __builtin_amdgcn_readfirstlane((__builtin_ctzll(r) + sh) & Mm1);
                 my_c = lane == L ? c : my_c;
@@ -325,17 +425,25 @@ static __global__ __launch_bounds__(64) void mid_fill_kernel(
         }
         pk[k & 3] = u;
         pw[k & 3] = w;
-        if ((k & 3) == 3) {
+        if ((k & 3) == 3 && lane < M) {
             d[(int64_t)(k >> 2) * 64] = make_uint2(pk[0] | (pk[1] << 16), pk[2] | (pk[3] << 16));
             if (dw) dw[(int64_t)(k >> 2) * 64] = make_float4(pw[0], pw[1], pw[2], pw[3]);
         }
     }
-    vtab[(int64_t)slot * 64 + lane] =
-        v >= 0 ? make_int2(v, __float_as_int((1.0f - alpha) * invd[v])) : make_int2(-1, 0);
+    if (lane < M) {
+        // a part of a split row is written through its partial slot, not here
+        vtab[(int64_t)slot * 64 + q] = (v >= 0 && tag == 0)
+                                           ? make_int2(v * C * 4, __float_as_int((1.0f - alpha) * invd[v]))
+                                           : make_int2(-1, 0);
+        if (tag > 0 && slot % kMidSlotCap == 0)
+            part_dst[(slot / kMidSlotCap) * kWave + q] = (n + 1) * C * 4 + (tag - 1) * C * 4;
+    }
 }
 
 struct MidArgs {
     const int32_t* plan;
+    const int32_t* part_dst;  // per wave and lane: LDS byte address of its slot-0 partial, or -1
+    const int4* comb;         // per split row: row address, scale, first partial address, parts
     const uint16_t* sell;
     const float* sellw;  // nullptr: unit weights
     const int2* vtab;
@@ -399,6 +507,9 @@ __global__ __launch_bounds__(kMidThreads) void ppr_mid_kernel(MidArgs a) {
     int sn[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) sn[c] = s0 + c < a.n_src ? (a.src ? a.src[s0 + c] : s0 + c) : -1;
+    int sa[C];  // LDS byte address of each source's row (-8: no source)
+#pragma unroll
+    for (int c = 0; c < C; ++c) sa[c] = sn[c] >= 0 ? sn[c] * C * 4 : -8;
 
     if (a.plan[kPlanFlag] != 0) {  // stream bound exceeded (repeated arcs): no result
         const float nan = __int_as_float(0x7fc00000);
@@ -426,6 +537,9 @@ __global__ __launch_bounds__(kMidThreads) void ppr_mid_kernel(MidArgs a) {
     __syncthreads();
 
     const int gtab = lane < KS ? a.plan[wv * kMidSlotCap + lane] : 0;
+    const int pdst = a.part_dst[tid];  // slot-0 partial target of this lane (parts of split rows)
+    int4 cmb = make_int4(-1, 0, 0, 0);  // split row this lane combines, if any
+    if (tid < a.plan[kPlanHubs]) cmb = a.comb[tid];
     const int64_t start = a.plan[kPlanStart + wv];
     using f4v = float __attribute__((ext_vector_type(4)));
     const gcptr<uint64_t> sbase = as_global(reinterpret_cast<const uint64_t*>(a.sell)) + start * 64 + lane;
@@ -437,14 +551,21 @@ __global__ __launch_bounds__(kMidThreads) void ppr_mid_kernel(MidArgs a) {
 
     float acc[KS][C];
     for (int it = 1; it < T; ++it) {
-        gcptr<uint64_t> sp = sbase + 2 * 64;
-        uint64_t q0 = sbase[0], q1 = sbase[64];
+        // ring of the next kMidPrefetch groups of this wave's stream (it runs
+        // on across slot boundaries: the wave's slices are stored in order)
+        constexpr int D = kMidPrefetch;
+        gcptr<uint64_t> sp = sbase + D * 64;
+        uint64_t q[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) q[j] = sbase[j * 64];
         gcptr<f4v> wp = nullptr;
-        f4v r0 = {0.f, 0.f, 0.f, 0.f}, r1 = r0;
+        f4v r[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) r[j] = f4v{1.f, 1.f, 1.f, 1.f};
         if (WEIGHTED) {
-            wp = wbase + 2 * 64;
-            r0 = wbase[0];
-            r1 = wbase[64];
+            wp = wbase + D * 64;
+#pragma unroll
+            for (int j = 0; j < D; ++j) r[j] = wbase[j * 64];
         }
 #pragma unroll
         for (int p = 0; p < KS; ++p) {
@@ -452,15 +573,16 @@ __global__ __launch_bounds__(kMidThreads) void ppr_mid_kernel(MidArgs a) {
             for (int c = 0; c < C; ++c) acc[p][c] = 0.f;
             const int gp = __builtin_amdgcn_readlane(gtab, p);
             for (int i = 0; i < gp; ++i) {
-                const uint64_t cur = q0;
-                q0 = q1;
-                q1 = *sp;
+                const uint64_t cur = q[0];
+#pragma unroll
+                for (int j = 0; j + 1 < D; ++j) q[j] = q[j + 1];
+                q[D - 1] = *sp;
                 sp += 64;
-                f4v cw = {1.f, 1.f, 1.f, 1.f};
+                f4v cw = r[0];
                 if (WEIGHTED) {
-                    cw = r0;
-                    r0 = r1;
-                    r1 = *wp;
+#pragma unroll
+                    for (int j = 0; j + 1 < D; ++j) r[j] = r[j + 1];
+                    r[D - 1] = *wp;
                     wp += 64;
                 }
                 const uint32_t lo = (uint32_t)cur, hi = (uint32_t)(cur >> 32);
@@ -469,25 +591,61 @@ __global__ __launch_bounds__(kMidThreads) void ppr_mid_kernel(MidArgs a) {
                 mid_arc<C, WEIGHTED>(L, hi & 0xffffu, cw.z, acc[p]);
                 mid_arc<C, WEIGHTED>(L, hi >> 16, cw.w, acc[p]);
             }
+            if (p == 0 && pdst >= 0) {  // a part of a split row: its sum goes to its partial slot
+                float* dst = reinterpret_cast<float*>(reinterpret_cast<char*>(L) + pdst);
+#pragma unroll
+                for (int c = 0; c < C; ++c) dst[c] = acc[0][c];
+            }
         }
-        __syncthreads();
+        // write-back: the slot table (LDS byte address of the row, scale
+        // (1-alpha)/d) is read in batches of 8 slots, each batch loaded one
+        // batch ahead; the first batch is in flight across the barrier
         const bool fin = it == T - 1;
         const uint32_t lane8 = (uint32_t)opaque(lane * 8);
-        int64_t vsb = 0;
+        constexpr int NB = (KS + 7) / 8;
+        uint64_t e[2][8];
 #pragma unroll
-        for (int p = 0; p < KS; ++p) {
-            if (p % 8 == 0) vsb = opaque_s(vt_wave + (int64_t)p * 512);
-            if (__builtin_amdgcn_readlane(gtab, p) > 0) {
-                const uint64_t e = *reinterpret_cast<gcptr<uint64_t>>(
-                    reinterpret_cast<gcptr<char>>(vsb) + lane8 + (p % 8) * 512);
-                const int v = (int)(uint32_t)e;
-                if (v >= 0) {
-                    const float sc = fin ? 1.0f : __int_as_float((int)(uint32_t)(e >> 32));
-                    float* dst = L + v * C;
+        for (int j = 0; j < 8; ++j)
+            if (j < KS)
+                e[0][j] = *reinterpret_cast<gcptr<uint64_t>>(reinterpret_cast<gcptr<char>>(opaque_s(vt_wave)) +
+                                                             lane8 + j * 512);
+        __syncthreads();
 #pragma unroll
-                    for (int c = 0; c < C; ++c) dst[c] = (acc[p][c] + (v == sn[c] ? alpha : 0.f)) * sc;
+        for (int bt = 0; bt < NB; ++bt) {
+            if (bt + 1 < NB) {
+                const int64_t vsb = opaque_s(vt_wave + (int64_t)(bt + 1) * 8 * 512);
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if ((bt + 1) * 8 + j < KS)
+                        e[(bt + 1) & 1][j] =
+                            *reinterpret_cast<gcptr<uint64_t>>(reinterpret_cast<gcptr<char>>(vsb) + lane8 + j * 512);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int p = bt * 8 + j;
+                if (p < KS && __builtin_amdgcn_readlane(gtab, p) > 0) {
+                    const int addr = (int)(uint32_t)e[bt & 1][j];
+                    if (addr >= 0) {
+                        const float sc = fin ? 1.0f : __int_as_float((int)(uint32_t)(e[bt & 1][j] >> 32));
+                        float* dst = reinterpret_cast<float*>(reinterpret_cast<char*>(L) + addr);
+#pragma unroll
+                        for (int c = 0; c < C; ++c) dst[c] = (acc[p][c] + (addr == sa[c] ? alpha : 0.f)) * sc;
+                    }
                 }
             }
+        }
+        if (cmb.x >= 0) {  // split row: its parts' partial sums in part order, in FP64
+            double x[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) x[c] = 0.0;
+            const float* pp = reinterpret_cast<const float*>(reinterpret_cast<const char*>(L) + cmb.z);
+            for (int j = 0; j < cmb.w; ++j)
+#pragma unroll
+                for (int c = 0; c < C; ++c) x[c] += (double)pp[j * C + c];
+            const float sc = fin ? 1.0f : __int_as_float(cmb.y);
+            float* dst = reinterpret_cast<float*>(reinterpret_cast<char*>(L) + cmb.x);
+#pragma unroll
+            for (int c = 0; c < C; ++c) dst[c] = ((float)x[c] + (cmb.x == sa[c] ? alpha : 0.f)) * sc;
         }
         __syncthreads();
     }
@@ -536,11 +694,14 @@ struct MidWs {
     int32_t* plan;        // kPlanInts
     int32_t* slice_goff;  // mid_slices(n)
     int32_t* slice_slot;  // mid_slices(n)
-    int2* vtab;           // kMidWaves * kMidSlotCap * 64
+    int2* vtab;           // kMidWaves * kMidSlotCap * 64: (LDS byte address of the row, scale)
     uint16_t* sell;       // mid_stream_groups * kMidGroup
     float* sellw;         // same, weighted graphs only
     int32_t* tmp_u;       // nnz: arcs bucketed by bank class
     float* tmp_w;         // nnz, weighted graphs only
+    RowEnt* vrows;        // n + kMidMaxParts: rows after splitting long rows
+    int4* comb;           // kMidMaxParts: one entry per split row
+    int32_t* part_dst;    // kMidWaves * 64: slot-0 partial targets
 };
 
 template <int C, bool W>
@@ -560,13 +721,18 @@ inline void mid_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, con
     hipLaunchKernelGGL(stream_deg_hist_kernel<kMidKeys>, dim3(nb), dim3(256), 0, s, g->row_ptr, n, w.hist);
     hipLaunchKernelGGL(stream_deg_scan_kernel<kMidKeys>, dim3(1), dim3(1024), 0, s, w.hist);
     hipLaunchKernelGGL(mid_row_order_kernel, dim3(1), dim3(1024), 0, s, g->row_ptr, n, w.hist, w.rows);
-    hipLaunchKernelGGL(mid_plan_kernel, dim3(1), dim3(1024), 0, s, w.rows, n, mid_slots(C),
+    hipLaunchKernelGGL(mid_split_kernel, dim3(1), dim3(1024), 0, s, w.rows, n, g->nnz, C, alpha, invd, w.plan,
+                       w.vrows, w.comb, w.part_dst);
+    hipLaunchKernelGGL(mid_plan_kernel, dim3(1), dim3(1024), 0, s, w.vrows, mid_slots(C),
                        mid_stream_groups(n, g->nnz), w.plan, w.slice_goff, w.slice_slot);
-    hipLaunchKernelGGL(mid_fill_kernel, dim3((unsigned)mid_slices(n)), dim3(64), 0, s, w.rows, g->col_idx,
-                       g->weight, invd, n, C, alpha, w.plan, w.slice_goff, w.slice_slot, w.tmp_u,
-                       weighted ? w.tmp_w : nullptr, w.sell, weighted ? w.sellw : nullptr, w.vtab);
+    hipLaunchKernelGGL(mid_fill_kernel, dim3((unsigned)(mid_slices(n + kMidMaxParts) * C)), dim3(64), 0, s,
+                       w.vrows, g->col_idx, g->weight, invd, n, C, alpha, w.plan, w.slice_goff, w.slice_slot,
+                       w.tmp_u, weighted ? w.tmp_w : nullptr, w.sell, weighted ? w.sellw : nullptr, w.vtab,
+                       w.part_dst);
     MidArgs a;
     a.plan = w.plan;
+    a.part_dst = w.part_dst;
+    a.comb = w.comb;
     a.sell = w.sell;
     a.sellw = weighted ? w.sellw : nullptr;
     a.vtab = w.vtab;

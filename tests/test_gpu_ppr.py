@@ -94,16 +94,66 @@ def test_kernel_size_boundaries(ops, n):
     assert np.abs(resid - res_o).max() <= 2e-6
 
 
-def test_mid_repeated_arcs_flagged(ops):
-    # a row listing one neighbour far more than n times breaks the mid-size
-    # kernel's bound on its padded arc copy: NaN outputs, ENONFINITE
-    n = 2400
-    reps = 50000
+@pytest.mark.parametrize("case", ["cl3000w", "cl12000", "cl25000", "star5000"])
+def test_mid_split_long_rows(ops, case):
+    # power-law graphs whose longest rows exceed a wave's share of a push: the
+    # mid-size kernel cuts them into parts whose partial sums it adds back in
+    # part order (4, 2 and 1 columns per block; a weighted case with a
+    # shuffled target subset; a star whose hub becomes hundreds of parts)
+    rng = np.random.default_rng(11)
+    tgt = None
+    if case == "cl3000w":
+        g0 = synth.chung_lu(3000, 2.1, 40, 9)
+        w = (0.5 + 1.5 * rng.random(g0.m_und)).astype(np.float32)
+        g = synth.build_graph(g0.n, g0.eu, g0.ev, w)
+        tgt = rng.permutation(g.n)[:777]
+    elif case == "cl12000":
+        g = synth.chung_lu(12000, 2.1, 30, 100 + 12000)
+    elif case == "cl25000":
+        g = synth.chung_lu(25000, 2.1, 20, 100 + 25000)
+    else:
+        n = 5000
+        g = synth.build_graph(n, np.zeros(n - 1, dtype=np.int64), np.arange(1, n))
+    src = synth.random_sources(g, 70, 3000 + g.n)
+    src[0] = int(np.argmax(np.diff(g.row_ptr)))  # the longest row is a source too
+    src = np.unique(src)
+    print(f"[split] {case} n={g.n} nnz={g.nnz} max degree={np.diff(g.row_ptr).max()}", flush=True)
+    ppr, dppr, T, resid = ops.ppr_matrix(_csr(ops, g), src, tgt=tgt, tol=1e-6, check_residual=True)
+    est, dppr_o, T_o, res_o, d = oracle_ppr(g, src, tol=1e-6)
+    assert T == T_o == 86
+    if tgt is not None:
+        est, dppr_o = est[:, tgt], dppr_o[:, tgt]
+    assert_ppr_close(ppr, dppr, est, dppr_o, d[src])
+    assert np.abs(resid - res_o).max() <= 2e-6
+
+
+def _repeated_arc_csr(ops, n, reps):
+    # nodes 0 and 1 joined by `reps` parallel arcs each way, all others isolated
     row_ptr = np.zeros(n + 1, dtype=np.int32)
     row_ptr[1] = reps
     row_ptr[2:] = 2 * reps
     col = np.concatenate([np.full(reps, 1), np.full(reps, 0)]).astype(np.int32)
-    csr = ops.Csr(n, len(col), torch.as_tensor(row_ptr, device="cuda"), torch.as_tensor(col, device="cuda"), None)
+    return ops.Csr(n, len(col), torch.as_tensor(row_ptr, device="cuda"), torch.as_tensor(col, device="cuda"), None)
+
+
+def test_mid_repeated_arcs(ops):
+    # rows far longer than n (repeated neighbours) are cut into parts like any
+    # long row; the walk is that of a two-node path, with node 5 isolated
+    csr = _repeated_arc_csr(ops, 2400, 5000)
+    ppr, _, T, resid = ops.ppr_matrix(csr, [0, 5], tol=1e-6, check_residual=True)
+    est, _, T_o, _, _ = oracle_ppr(synth.build_graph(2, [0], [1]), [0], T=T)
+    p = ppr.double().cpu().numpy()
+    assert abs(p[0, 0] - est[0, 0]) <= 1e-6 and abs(p[0, 1] - est[0, 1]) <= 1e-6
+    assert np.abs(p[0, 2:]).max() == 0.0
+    assert abs(p[1, 5] - (1 - (1 - ALPHA) ** T)) <= 1e-6
+    assert np.abs(resid - (1 - ALPHA) ** T).max() <= 2e-6
+
+
+def test_mid_repeated_arcs_flagged(ops):
+    # at n = 10207 the iterate of 4 columns fills the LDS, leaving no room for
+    # partial sums, so the rows cannot be cut: the padded arc copy would
+    # exceed its workspace bound, which the kernel reports as NaN outputs
+    csr = _repeated_arc_csr(ops, 10207, 200000)
     from paper_2112_14944_amd._lib import PPR_ENONFINITE, PprvizError
     with pytest.raises(PprvizError) as ei:
         ops.ppr_matrix(csr, [0, 5], tol=1e-6, check_residual=True)
