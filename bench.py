@@ -168,6 +168,40 @@ def spmm_all_pairs(ops, dev, n=20000, gamma=2.5, avg_degree=20, tol=1e-7, reps=2
                 frac=alg / (best * 1e-3) / 1e9 / PEAK_HBM_GBS, work=f"{alg:.4g} B over {T - 1} pushes", nnz=nnz)
 
 
+def spmm_large(ops, dev, n=1_000_000, gamma=2.2, avg_degree=30, n_src=4096, tol=1e-6, reps=2):
+    """The multi-source SpMM above the LDS sizes: Chung-Lu n = 10^6, exponent
+    2.2, mean degree 30 (about 3e7 arcs), PPR from 4096 seeded sources to L1
+    1e-6, accumulated at the 4096 sources as targets, one whole ppr_matrix call.
+    The iterate (4096 columns of 10^6 nodes, 16.4 GB per buffer) lives in HBM
+    (stream_step_kernel, one launch per push).  Algorithmic bytes per push:
+    8 n S + 4 nnz + 8 (n + 1)."""
+    import torch
+    import synth
+
+    g = synth.chung_lu(n, gamma, avg_degree, synth.BASE_SEED + 4)
+    src = synth.random_sources(g, n_src, synth.BASE_SEED + 5)
+    csr = ops.Csr.from_graph(g, dev)
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, dppr, T, _ = ops.ppr_matrix(csr, src, tgt=src, alpha=ALPHA, tol=tol, want_ppr=False, want_dppr=True)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+        del dppr
+    nnz = int(g.col_idx.shape[0])
+    alg = (T - 1) * (8.0 * n * n_src + 4.0 * nnz + 8.0 * (n + 1))
+    return dict(workload=f"chung_lu n={n} gamma={gamma} mean degree {avg_degree}, {n_src} sources, "
+                         f"L1 {tol:g} (T={T}), DPPR among the sources, whole ppr_matrix call",
+                kernel="stream_step_kernel", ms=best, bound="hbm", unit="GB/s",
+                achieved=alg / (best * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
+                frac=alg / (best * 1e-3) / 1e9 / PEAK_HBM_GBS, work=f"{alg:.4g} B over {T - 1} pushes", nnz=nnz)
+
+
 def counters_pass(ops, b, x0, dev):
     """One eager batched pass, one all-pairs SpMM run (n = 20000), then a plain 1 GiB
     device copy, for rocprofv3 --pmc runs: the copy's FETCH_SIZE / WRITE_SIZE
@@ -198,6 +232,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the stage-timing pass")
     ap.add_argument("--no-spmm", action="store_true", help="skip the all-pairs SpMM measurement (n = 20000)")
+    ap.add_argument("--no-spmm-large", action="store_true",
+                    help="skip the 4096-source SpMM on the n = 10^6 graph")
     ap.add_argument("--counters", action="store_true",
                     help="one eager batched pass plus a 1 GiB calibration copy (for rocprofv3 --pmc), no timing")
     args = ap.parse_args()
@@ -334,6 +370,15 @@ def main():
         spmm = spmm_all_pairs(ops, dev)
         log(f"all-pairs SpMM (n = 20000): {spmm['ms']:.1f} ms, {spmm['achieved']:.0f} GB/s algorithmic")
 
+    spmm_big = None
+    if not args.no_spmm_large:
+        del bufs
+        plan.close()
+        plan = None
+        torch.cuda.empty_cache()
+        spmm_big = spmm_large(ops, dev)
+        log(f"4096-source SpMM (n = 10^6): {spmm_big['ms']:.1f} ms, {spmm_big['achieved']:.0f} GB/s algorithmic")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a sample ...")
@@ -363,10 +408,12 @@ def main():
         "roofline": roof,
         "stages": stages,
         "spmm": spmm,
+        "spmm_large": spmm_big,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    plan.close()
+    if plan is not None:
+        plan.close()
 
 
 if __name__ == "__main__":

@@ -393,7 +393,7 @@ template <typename Cursor>
 static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     BatchWs t;
     t.rows = c.template take<RowEnt>((size_t)b->n_nodes);
-    t.col_r = c.template take<int32_t>((size_t)(b->nnz + kArcPad));
+    t.col_r = c.template take<int32_t>((size_t)(b->nnz + (int64_t)kArcRowPad * b->n_nodes + kArcPad));
     t.deg = c.template take<float>((size_t)b->n_nodes);
     t.invd = c.template take<float>((size_t)b->n_nodes);
     // 1/Delta pool with rows padded to 32 floats: sum_g k (k + 31) <= pool + 31 n_nodes
@@ -457,6 +457,8 @@ static ppr_status batch_validate(const ppr_batch* b, float alpha, int32_t max_it
     if (!x0 || !x_out || x0 == x_out || !dppr_pool || !delta_pool) return PPR_EINVAL;
     if (b->max_n < 1 || b->pool_size < b->n_nodes) return PPR_EINVAL;
     if (b->max_n > kBatchMaxN) return PPR_EUNSUPPORTED;
+    // positions in the padded arc copy are int32
+    if (b->nnz + (int64_t)kArcRowPad * (b->n_nodes + 1) + kArcPad >= (int64_t)INT32_MAX) return PPR_EUNSUPPORTED;
     return PPR_OK;
 }
 

@@ -38,8 +38,8 @@ void ppr_ws_layout(Cursor& c, int n, int64_t nnz, bool weighted, int n_src, PprW
     const bool res = res_cols_for(n) != 0;
     const bool mid = mid_cols_for(n) != 0;
     if (res) {
-        t.col_r = c.template take<int32_t>((size_t)(nnz + kArcPad));
-        t.w_r = weighted ? c.template take<float>((size_t)(nnz + kArcPad)) : nullptr;
+        t.col_r = c.template take<int32_t>((size_t)(nnz + (int64_t)kArcRowPad * n + kArcPad));
+        t.w_r = weighted ? c.template take<float>((size_t)(nnz + (int64_t)kArcRowPad * n + kArcPad)) : nullptr;
     }
     if (mid) {
         const int64_t groups = mid_stream_groups(n, nnz);

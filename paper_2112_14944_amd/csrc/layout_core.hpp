@@ -246,22 +246,28 @@ __device__ __forceinline__ void pair_tile_ij(int t, int& I, int& J) {
 
 // Per-tile state of one wave in pair_tile_body.
 struct PairTileCtx {
+    __amdgpu_buffer_rsrc_t mr;  // rows 64 I .. of the subgraph's matrix
     int lane, i, j0, ncol, I, J, T, cc, cp;
     bool row_ok;
     float2 xi;
 };
 
 // Loads of one 8-column chunk: m[j][i] for the lane's row and the chunk's
-// columns (one coalesced 256-byte row segment per column), and X_j.
+// columns (one coalesced 256-byte row segment per column), and X_j.  The
+// matrix is read through a buffer resource whose base is row 64 I, with the
+// column's offset as a scalar and the lane's as the one vector offset, so
+// that no per-column addresses take vector registers.
 template <bool POS, bool FULL>
-__device__ __forceinline__ void pair_load(const PairTileCtx& t, const float* __restrict__ mcol, int64_t ld,
+__device__ __forceinline__ void pair_load(const PairTileCtx& t, int64_t ld,
                                           int32_t k, const float2* __restrict__ x, int q, float (&mv)[kPTChunk],
                                           float2 (&xj)[kPTChunk]) {
     const int jq = t.j0 + q * kPTChunk;
 #pragma unroll
     for (int s = 0; s < kPTChunk; ++s) {
         const bool col_ok = FULL || (q * kPTChunk + s < t.ncol);
-        mv[s] = (col_ok && t.row_ok) ? mcol[(int64_t)(jq + s) * ld] : 0.f;
+        mv[s] = (col_ok && t.row_ok) ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                                           t.mr, t.lane * 4, (int)((int64_t)(jq + s) * ld * 4), 0))
+                                     : 0.f;
         if (POS) xj[s] = x[FULL ? jq + s : min(jq + s, k - 1)];
     }
 }
@@ -372,17 +378,18 @@ __device__ __forceinline__ void pair_tile_body(const float* __restrict__ m, int6
     t.T = T;
     t.cc = t.lane >> 3;
     t.cp = t.lane & 7;
-    const float* __restrict__ mcol = m + t.i;
+    t.mr = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(m + (int64_t)I * kPT), 0,
+                                             (int)((int64_t)k * ld * 4), 0x00020000);
     const int nq = (t.ncol + kPTChunk - 1) / kPTChunk;
     float ax = 0.f, ay = 0.f, aw = 0.f;
     float ma[kPTChunk], mb[kPTChunk];
     float2 xa[kPTChunk], xb[kPTChunk];
-    pair_load<POS, FULL>(t, mcol, ld, k, x, 0, ma, xa);
+    pair_load<POS, FULL>(t, ld, k, x, 0, ma, xa);
     for (int q = 0; q < nq; q += 2) {
-        if (q + 1 < nq) pair_load<POS, FULL>(t, mcol, ld, k, x, q + 1, mb, xb);
+        if (q + 1 < nq) pair_load<POS, FULL>(t, ld, k, x, q + 1, mb, xb);
         pair_chunk<INV, MODE, DIAG, FULL>(t, q, ma, xa, ax, ay, aw, px, py, pw, L);
         if (q + 1 < nq) {
-            if (q + 2 < nq) pair_load<POS, FULL>(t, mcol, ld, k, x, q + 2, ma, xa);
+            if (q + 2 < nq) pair_load<POS, FULL>(t, ld, k, x, q + 2, ma, xa);
             pair_chunk<INV, MODE, DIAG, FULL>(t, q + 1, mb, xb, ax, ay, aw, px, py, pw, L);
         }
     }

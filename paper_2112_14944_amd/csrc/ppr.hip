@@ -27,7 +27,9 @@ __global__ void degree_kernel(const int32_t* __restrict__ row_ptr, const float* 
 }
 
 // Row table of the resident tile: rows sorted by degree, longest first, ties
-// by row id; one block per graph.
+// by row id; one block per graph.  rs/re locate the row in the tile's arc
+// copy, where global row v starts at row_ptr[v] + kArcRowPad v (room to pad
+// each row, see bank_order_kernel).
 __global__ __launch_bounds__(256) void row_table_kernel(const int32_t* __restrict__ row_ptr,
                                                        const int64_t* __restrict__ node_off, int32_t n_single,
                                                        RowEnt* __restrict__ table) {
@@ -67,7 +69,9 @@ __global__ __launch_bounds__(256) void row_table_kernel(const int32_t* __restric
     }
     for (int p = threadIdx.x; p < n; p += 256) {
         const int v = (int)(key[p] & 4095u);
-        table[base + p] = RowEnt{row_ptr[base + v], row_ptr[base + v + 1], v, 0};
+        const int64_t gv = base + v;
+        const int rs = row_ptr[gv] + kArcRowPad * (int)gv;
+        table[base + p] = RowEnt{rs, rs + (row_ptr[gv + 1] - row_ptr[gv]), v, 0};
     }
 }
 
@@ -80,7 +84,10 @@ __global__ __launch_bounds__(256) void row_table_kernel(const int32_t* __restric
 // while that class lasts, so the four reads of a pass fall in different bank
 // groups.  Only the order of each row's arcs changes (and with it the order of
 // the FP32 sum).  The copy holds each arc's LDS byte offset in the tile,
-// (u - first node) * 4 COLS, not its node id.
+// (u - first node) * 4 COLS, not its node id, and each row with arcs is
+// padded with the offset of the tile's zero row to at least 16 arcs and to a
+// multiple of 8, so the tile's chunks (a full 16-arc chunk first, then full
+// chunks and a last one of 16 or 8) need no bound checks.
 __global__ __launch_bounds__(256) void bank_order_kernel(const int32_t* __restrict__ col_idx,
                                                         const float* __restrict__ weight,
                                                         const int64_t* __restrict__ node_off, int32_t n_graphs,
@@ -104,11 +111,18 @@ __global__ __launch_bounds__(256) void bank_order_kernel(const int32_t* __restri
     const int M = cols == 16 ? 4 : (cols == 32 ? 2 : 1);  // bank classes
     const int stride = (cols > 0 ? cols : 16) * 4;        // LDS bytes per row
     const RowEnt r = table[i];
-    const int rs = r.rs, re = r.re;
+    const int shift = kArcRowPad * (int)(base + r.v);  // copy position - CSR position
+    const int rs = r.rs - shift, re = r.re - shift;
+    const int deg = re - rs;
+    const int pad_end = r.rs + (deg == 0 ? 0 : max(16, (deg + 7) / 8 * 8));
+    for (int m = r.re; m < pad_end; ++m) {
+        col_out[m] = n * stride;
+        if (w_out) w_out[m] = 0.f;
+    }
     if (M == 1) {
         for (int e = rs; e < re; ++e) {
-            col_out[e] = (int)(col_idx[e] - base) * stride;
-            if (w_out) w_out[e] = weight[e];
+            col_out[e + shift] = (int)(col_idx[e] - base) * stride;
+            if (w_out) w_out[e + shift] = weight[e];
         }
         return;
     }
@@ -123,8 +137,8 @@ __global__ __launch_bounds__(256) void bank_order_kernel(const int32_t* __restri
         int c = (m - rs + p) & (M - 1);
         for (int t = 0; t < M && next[c] >= re; ++t) c = (c + 1) & (M - 1);
         const int e = next[c];
-        col_out[m] = (int)(col_idx[e] - base) * stride;
-        if (w_out) w_out[m] = weight[e];
+        col_out[m + shift] = (int)(col_idx[e] - base) * stride;
+        if (w_out) w_out[m + shift] = weight[e];
         int f = e + 1;
         while (f < re && (int)((col_idx[f] - base) & (M - 1)) != c) ++f;
         next[c] = f;

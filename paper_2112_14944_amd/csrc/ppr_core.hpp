@@ -22,6 +22,7 @@ namespace pprviz {
 constexpr int kResThreads = 1024;
 constexpr int kResWaves = kResThreads / kWave;
 constexpr int kArcPad = 16;  // padding entries after the tile's arc array (chunk loads read ahead)
+constexpr int kArcRowPad = 16;  // room per row in the tile's arc copy for padding the row
 constexpr int kResMaxK = 9;  // rows per lane (4 columns each) held in registers across a step
 
 // Tile geometry.  Lanes work in quads: a quad owns 16 columns of one row, each
@@ -79,7 +80,7 @@ __device__ __forceinline__ RowEnt load_row(gcptr<RowEnt> p, int64_t i) {
 struct ResArgs {
     const RowEnt* rows;      // per graph, rows in slot order (row_table_kernel)
     const int32_t* row_ptr;  // global CSR row pointers
-    const int32_t* col_idx;  // per arc (bank-class order, 16 entries of padding): LDS byte offset of the neighbour's row
+    const int32_t* col_idx;  // arc copy (bank_order_kernel): LDS byte offset of the neighbour's row, rows padded
     const float* weight;     // arc weights, or nullptr
     const float* invd;       // per global node: 1/d, or 1 for a node without arcs
     const float* deg;        // per global node: weighted degree d
@@ -171,25 +172,25 @@ struct ResLds {
 };
 
 // Loads one 16-arc chunk of a quad's row (arcs e0 + 4i + q for i = 0..3).
+// Rows of the arc copy are padded with the zero row's offset to at least 16
+// arcs and to a multiple of 8, and a later chunk with at most 8 arcs left
+// uses only lanes 0 and 1, so every arc the gather uses is a real arc or the
+// zero row: no bound checks.
 template <bool WEIGHTED>
-__device__ __forceinline__ void load_chunk(gcptr<int32_t> pc, gcptr<float> pw, int e0, int re, int q, int dummy,
-                                           int& r0, int& r1, int& r2, int& r3, float& w0, float& w1, float& w2,
-                                           float& w3) {
+__device__ __forceinline__ void load_chunk(gcptr<int32_t> pc, gcptr<float> pw, int e0, int q, int& r0, int& r1,
+                                           int& r2, int& r3, float& w0, float& w1, float& w2, float& w3) {
     // lane q takes the 4 consecutive arcs e0 + 4q .. e0 + 4q + 3; the arc
     // array is padded by 16 entries, so the loads need no guard
     const int e = e0 + 4 * q;
-    const int lim = re - e;
-    const int v0 = pc[e], v1 = pc[e + 1], v2 = pc[e + 2], v3 = pc[e + 3];
-    r0 = lim > 0 ? v0 : dummy;
-    r1 = lim > 1 ? v1 : dummy;
-    r2 = lim > 2 ? v2 : dummy;
-    r3 = lim > 3 ? v3 : dummy;
+    r0 = pc[e];
+    r1 = pc[e + 1];
+    r2 = pc[e + 2];
+    r3 = pc[e + 3];
     if (WEIGHTED) {
-        const float u0 = pw[e], u1 = pw[e + 1], u2 = pw[e + 2], u3 = pw[e + 3];
-        w0 = lim > 0 ? u0 : 0.f;
-        w1 = lim > 1 ? u1 : 0.f;
-        w2 = lim > 2 ? u2 : 0.f;
-        w3 = lim > 3 ? u3 : 0.f;
+        w0 = pw[e];
+        w1 = pw[e + 1];
+        w2 = pw[e + 2];
+        w3 = pw[e + 3];
     }
 }
 
@@ -255,7 +256,6 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
         const int r0 = opaque(row0);
         const int64_t b = opaque_s(base);
         const int n = opaque_s32(t.n);
-        const int dummy = n * STRIDE;
         // Rows are visited in slot order (degree-sorted, so the rows that
         // share a pass have similar length).  Row-level software pipeline:
         // the first chunk of slot k+1 and the table entry of slot k+2 are
@@ -265,7 +265,7 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
         if (r0 + RPP < n) e2 = load_row(rows, b + r0 + RPP);
         int p0 = 0, p1 = 0, p2 = 0, p3 = 0;
         float pw0 = 0.f, pw1 = 0.f, pw2 = 0.f, pw3 = 0.f;
-        load_chunk<WEIGHTED>(pc, pw, e1.rs, e1.re, q, dummy, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
+        load_chunk<WEIGHTED>(pc, pw, e1.rs, q, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
 #pragma unroll
         for (int k = 0; k < kResMaxK; ++k) {
             if (k * RPP < n) {
@@ -275,7 +275,7 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
                 const float cw0 = pw0, cw1 = pw1, cw2 = pw2, cw3 = pw3;
                 e1 = e2;
                 if (k + 1 < kResMaxK && slot + RPP < n)
-                    load_chunk<WEIGHTED>(pc, pw, e1.rs, e1.re, q, dummy, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
+                    load_chunk<WEIGHTED>(pc, pw, e1.rs, q, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
                 if (k + 2 < kResMaxK && slot + 2 * RPP < n) e2 = load_row(rows, b + slot + 2 * RPP);
                 if (slot < n) {
                     vs[k] = v;
@@ -290,7 +290,7 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
                     for (int e0 = rs + 16; e0 < re; e0 += 16) {
                         int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
                         float dw0 = 0.f, dw1 = 0.f, dw2 = 0.f, dw3 = 0.f;
-                        load_chunk<WEIGHTED>(pc, pw, e0, re, q, dummy, d0, d1, d2, d3, dw0, dw1, dw2, dw3);
+                        load_chunk<WEIGHTED>(pc, pw, e0, q, d0, d1, d2, d3, dw0, dw1, dw2, dw3);
                         if (re - e0 > 8) {
                             gather_chunk<WEIGHTED, 2>(lds, d0, d1, d2, d3, dw0, dw1, dw2, dw3, cbyte, acc);
                         } else {
