@@ -51,6 +51,7 @@ void ppr_ws_layout(Cursor& c, int n, int64_t nnz, bool weighted, int n_src, PprW
         t.mid.vrows = c.template take<RowEnt>((size_t)n + kMidMaxParts);
         t.mid.comb = c.template take<int4>(kMidMaxParts);
         t.mid.part_dst = c.template take<int32_t>(kMidWaves * kWave);
+        t.mid.rowpos = c.template take<int32_t>(n);
         t.mid.vtab = c.template take<int2>((size_t)kMidWaves * kMidSlotCap * 64);
         t.mid.sell = c.template take<uint16_t>((size_t)(groups * kMidGroup));
         t.mid.sellw = weighted ? c.template take<float>((size_t)(groups * kMidGroup)) : nullptr;

@@ -305,6 +305,11 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
                 }
             }
         }
+        // the slots' scales (constant for the tile) are read before the
+        // barrier, all at once, instead of one LDS round trip per slot after it
+        float sc[kResMaxK];
+#pragma unroll
+        for (int k = 0; k < kResMaxK; ++k) sc[k] = L.scale[max(vs[k], 0)];
         __syncthreads();
         const int r1 = opaque(row0);
         const int n1 = opaque_s32(t.n);
@@ -314,9 +319,8 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
                 const int slot = r1 + k * RPP;
                 if (slot < n1) {
                     const int v = vs[k];
-                    const float sc = L.scale[v];
                     *reinterpret_cast<float4*>(reinterpret_cast<char*>(lds) + v * STRIDE + cbyte) =
-                        make_float4(xr[k].x * sc, xr[k].y * sc, xr[k].z * sc, xr[k].w * sc);
+                        make_float4(xr[k].x * sc[k], xr[k].y * sc[k], xr[k].z * sc[k], xr[k].w * sc[k]);
                 }
             }
         }

@@ -98,7 +98,8 @@ static __global__ __launch_bounds__(1024) void mid_split_kernel(const RowEnt* __
                                                                const float* __restrict__ invd,
                                                                int32_t* __restrict__ plan, RowEnt* __restrict__ vrows,
                                                                int4* __restrict__ comb,
-                                                               int32_t* __restrict__ part_dst) {
+                                                               int32_t* __restrict__ part_dst,
+                                                               int32_t* __restrict__ rowpos) {
     __shared__ int32_t hub_pb[kMidMaxParts];
     __shared__ int64_t sD;
     __shared__ int32_t sH, sP;
@@ -148,6 +149,7 @@ static __global__ __launch_bounds__(1024) void mid_split_kernel(const RowEnt* __
             vrows[pb + j] = RowEnt{a, b, e.v, pb + j + 1};
         }
         comb[h] = make_int4(e.v * C * 4, __float_as_int((1.0f - alpha) * invd[e.v]), part0 + pb * C * 4, m);
+        rowpos[e.v] = -1;
     }
     for (int i = H + tid; i < n; i += 1024) {
         const RowEnt e = rows[i];
@@ -309,7 +311,7 @@ static __global__ __launch_bounds__(64) void mid_fill_kernel(
     const float* __restrict__ invd, int32_t n, int32_t C, float alpha, const int32_t* __restrict__ plan,
     const int32_t* __restrict__ slice_goff, const int32_t* __restrict__ slice_slot, int32_t* __restrict__ tmp_u,
     float* __restrict__ tmp_w, uint16_t* __restrict__ sell, float* __restrict__ sellw, int2* __restrict__ vtab,
-    int32_t* __restrict__ part_dst) {
+    int32_t* __restrict__ part_dst, int32_t* __restrict__ rowpos) {
     __shared__ int32_t beg[kWave][kWave];  // per lane and class: first bucketed arc
     __shared__ int32_t pos[kWave][kWave];  // per lane and class: one past the last remaining arc
     const int lane = threadIdx.x;
@@ -437,11 +439,13 @@ static __global__ __launch_bounds__(64) void mid_fill_kernel(
                                            : make_int2(-1, 0);
         if (tag > 0 && slot % kMidSlotCap == 0)
             part_dst[(slot / kMidSlotCap) * kWave + q] = (n + 1) * C * 4 + (tag - 1) * C * 4;
+        if (v >= 0 && tag == 0) rowpos[v] = slot * 64 + q;
     }
 }
 
 struct MidArgs {
     const int32_t* plan;
+    const int32_t* rowpos;    // per node: its slot and lane, -1 when split
     const int32_t* part_dst;  // per wave and lane: LDS byte address of its slot-0 partial, or -1
     const int4* comb;         // per split row: row address, scale, first partial address, parts
     const uint16_t* sell;
@@ -507,9 +511,19 @@ __global__ __launch_bounds__(kMidThreads) void ppr_mid_kernel(MidArgs a) {
     int sn[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) sn[c] = s0 + c < a.n_src ? (a.src ? a.src[s0 + c] : s0 + c) : -1;
+    const int wvu = __builtin_amdgcn_readfirstlane(wv);
     int sa[C];  // LDS byte address of each source's row (-8: no source)
 #pragma unroll
     for (int c = 0; c < C; ++c) sa[c] = sn[c] >= 0 ? sn[c] * C * 4 : -8;
+    // slot and lane holding each source's row (-1: none, or a split row,
+    // which its combining lane handles)
+    int sslot[C], slane[C];  // slot of this wave (-1: another wave's or none) and lane
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int sp = __builtin_amdgcn_readfirstlane(sn[c] >= 0 ? a.rowpos[sn[c]] : -1);
+        sslot[c] = (sp >= 0 && (sp >> 6) / kMidSlotCap == wvu) ? (sp >> 6) % kMidSlotCap : -1;
+        slane[c] = sp & 63;
+    }
 
     if (a.plan[kPlanFlag] != 0) {  // stream bound exceeded (repeated arcs): no result
         const float nan = __int_as_float(0x7fc00000);
@@ -546,8 +560,7 @@ __global__ __launch_bounds__(kMidThreads) void ppr_mid_kernel(MidArgs a) {
     const gcptr<f4v> wbase = WEIGHTED ? as_global(reinterpret_cast<const f4v*>(a.sellw)) + start * 64 + lane : nullptr;
     // slot table of this wave: a scalar base per 8 slots plus the lane's
     // byte offset, so that its addresses take no vector registers
-    const int64_t vt_wave = (int64_t)reinterpret_cast<uintptr_t>(a.vtab) +
-                            (int64_t)__builtin_amdgcn_readfirstlane(wv) * kMidSlotCap * 64 * 8;
+    const int64_t vt_wave = (int64_t)reinterpret_cast<uintptr_t>(a.vtab) + (int64_t)wvu * kMidSlotCap * 64 * 8;
 
     float acc[KS][C];
     for (int it = 1; it < T; ++it) {
@@ -624,12 +637,18 @@ __global__ __launch_bounds__(kMidThreads) void ppr_mid_kernel(MidArgs a) {
             for (int j = 0; j < 8; ++j) {
                 const int p = bt * 8 + j;
                 if (p < KS && __builtin_amdgcn_readlane(gtab, p) > 0) {
+                    // the restart term alpha at the block's source rows: a
+                    // wave-uniform test of the slot, then the one lane
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        if (opaque_s32(sslot[c]) == p)
+                            if (lane == slane[c]) acc[p][c] += alpha;
                     const int addr = (int)(uint32_t)e[bt & 1][j];
                     if (addr >= 0) {
                         const float sc = fin ? 1.0f : __int_as_float((int)(uint32_t)(e[bt & 1][j] >> 32));
                         float* dst = reinterpret_cast<float*>(reinterpret_cast<char*>(L) + addr);
 #pragma unroll
-                        for (int c = 0; c < C; ++c) dst[c] = (acc[p][c] + (addr == sa[c] ? alpha : 0.f)) * sc;
+                        for (int c = 0; c < C; ++c) dst[c] = acc[p][c] * sc;
                     }
                 }
             }
@@ -702,6 +721,7 @@ struct MidWs {
     RowEnt* vrows;        // n + kMidMaxParts: rows after splitting long rows
     int4* comb;           // kMidMaxParts: one entry per split row
     int32_t* part_dst;    // kMidWaves * 64: slot-0 partial targets
+    int32_t* rowpos;      // n: (wave * kMidSlotCap + slot) * 64 + lane of each row, -1 for split rows
 };
 
 template <int C, bool W>
@@ -722,16 +742,17 @@ inline void mid_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, con
     hipLaunchKernelGGL(stream_deg_scan_kernel<kMidKeys>, dim3(1), dim3(1024), 0, s, w.hist);
     hipLaunchKernelGGL(mid_row_order_kernel, dim3(1), dim3(1024), 0, s, g->row_ptr, n, w.hist, w.rows);
     hipLaunchKernelGGL(mid_split_kernel, dim3(1), dim3(1024), 0, s, w.rows, n, g->nnz, C, alpha, invd, w.plan,
-                       w.vrows, w.comb, w.part_dst);
+                       w.vrows, w.comb, w.part_dst, w.rowpos);
     hipLaunchKernelGGL(mid_plan_kernel, dim3(1), dim3(1024), 0, s, w.vrows, mid_slots(C),
                        mid_stream_groups(n, g->nnz), w.plan, w.slice_goff, w.slice_slot);
     hipLaunchKernelGGL(mid_fill_kernel, dim3((unsigned)(mid_slices(n + kMidMaxParts) * C)), dim3(64), 0, s,
                        w.vrows, g->col_idx, g->weight, invd, n, C, alpha, w.plan, w.slice_goff, w.slice_slot,
                        w.tmp_u, weighted ? w.tmp_w : nullptr, w.sell, weighted ? w.sellw : nullptr, w.vtab,
-                       w.part_dst);
+                       w.part_dst, w.rowpos);
     MidArgs a;
     a.plan = w.plan;
     a.part_dst = w.part_dst;
+    a.rowpos = w.rowpos;
     a.comb = w.comb;
     a.sell = w.sell;
     a.sellw = weighted ? w.sellw : nullptr;
