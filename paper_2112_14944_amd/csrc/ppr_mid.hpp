@@ -8,18 +8,24 @@
 // synchronous update as in the other kernels (Section 3.3's power iteration):
 //     X_{t+1}[v] = alpha [v == s] + sum_{u in N(v)} w_vu Y_t[u].
 //
-// Rows are sorted by degree (largest first) and cut into slices of 64, one
-// row per lane, so the rows of a slice have nearly equal arc counts.  The
-// arcs of a slice are stored lane-interleaved (a sliced-ELL layout): group g
-// of the slice holds arcs 4g .. 4g+3 of each of its 64 rows, 4 16-bit entries
-// per lane, so one 8-byte load per lane reads 4 arcs of its row and a wave
-// load is one contiguous 512-byte segment.  An entry is the LDS float index
-// u * C of the neighbour's row; rows shorter than the slice point at a zero
-// row.  Slices are dealt to the block's 16 waves longest first, each to the
-// least loaded wave with a free slot (at most KS per wave), and each wave's
-// slices are stored one after another, so a wave reads one contiguous stream
-// per push.  A lane keeps the sums of its KS rows in registers until every
-// wave has finished gathering, then writes them back (synchronous update).
+// Preparation (once per call, on the device):
+//  - rows are sorted by degree, largest first, ties by id (stable scatter);
+//  - rows longer than a wave's fair share are cut into parts whose partial
+//    sums are added back in a fixed order (mid_split_kernel);
+//  - the rows are cut into slices of 64, one row per lane, so the rows of a
+//    slice have nearly equal arc counts, and the slices are dealt to the
+//    block's 16 waves longest first (mid_plan_kernel);
+//  - the arcs of a slice are stored lane-interleaved (a sliced-ELL layout):
+//    group g of the slice holds arcs 4g .. 4g+3 of each of its 64 rows, 4
+//    16-bit entries per lane, so one 8-byte load per lane reads 4 arcs of its
+//    row and a wave load is one contiguous 512-byte segment.  An entry is the
+//    LDS float index u * C of the neighbour's row; rows shorter than the
+//    slice point at a zero row.  Within a row, arcs are placed by LDS bank
+//    class so that the lanes of one LDS pass read different banks
+//    (mid_fill_kernel).  Each wave's slices are stored one after another, so
+//    a wave reads one contiguous stream per push.
+// A lane keeps the sums of its KS rows in registers until every wave has
+// finished gathering, then writes them back (synchronous update).
 #pragma once
 
 #include "ppr_core.hpp"
@@ -54,11 +60,11 @@ __host__ __device__ inline int64_t mid_slices(int n) { return (n + 63) / 64; }
 // Bound on the stream's groups.  With rows sorted by degree, slice i >= 1 is
 // no wider than the smallest row of slice i-1, so 64 * width(i) is at most
 // the arc count of slice i-1; the first slice adds at most 64 * (largest
-// degree), and rounding up to whole groups at most 256 entries per slice.  The largest
-// degree is at most n when no row lists a neighbour twice; a graph that breaks
-// the bound is flagged by the plan and gets NaN outputs.
-// The parts of split rows (below) fill at most 16 slices, each at most as
-// wide as the largest degree.
+// degree), and rounding up to whole groups at most 256 entries per slice.
+// The parts of split rows fill at most 16 more slices, each at most as wide
+// as the largest degree.  The largest degree is at most n when no row lists
+// a neighbour twice; a graph that breaks the bound is flagged by the plan and
+// gets NaN outputs.
 inline int64_t mid_stream_groups(int n, int64_t nnz) {
     const int64_t maxdeg = nnz < (int64_t)n ? nnz : (int64_t)n;
     return (64 * 17 * (maxdeg + 4) + nnz + kMidGroup * mid_slices(n + kMidMaxParts) + kMidGroup - 1) / kMidGroup +
@@ -74,20 +80,20 @@ constexpr int kPlanRows = kPlanFlag + 1;
 constexpr int kPlanHubs = kPlanRows + 1;
 constexpr int kPlanInts = kPlanHubs + 1;
 
-// Split of long rows.  One push costs a block as long as its busiest wave
-// takes, and a wave holding the slice of the longest rows can take far longer
-// than the mean when a few rows have hundreds of arcs.  Rows longer than D
-// arcs are therefore cut into parts of D arcs (the last part shorter), each
-// part a row of its own, placed ahead of all other rows so that they fill
-// the first (at most 16) slices, which the deal below gives to slot 0 of
-// waves 0..15.  After slot 0, a part's lane writes its sum to a partial slot
-// in LDS just past the iterate; after the push's barrier, one lane per split
-// row adds the partials in part order (a fixed order) in FP64, so that a row
-// of thousands of arcs is summed no less accurately than a short one, and
-// writes the row.  D
-// starts at half a wave's mean share of the arcs and doubles until the parts
-// fit the spare LDS after the iterate and the first 16 slices; nothing is
-// split when the longest row fits in a wave's mean share.
+// Split of long rows.  A slice is as wide as its longest row, so a slice of
+// rows with hundreds of arcs gives its wave far more work than the others in
+// each push, and its deal (one wave per slice pass, below) takes as long.
+// Rows longer than D arcs are therefore cut into parts of D arcs (the last
+// part shorter), each part a row of its own, placed ahead of all other rows
+// so that they fill the first (at most 16) slices, which the deal gives to
+// slot 0 of waves 0..15.  After slot 0, a part's lane writes its sum to a
+// partial slot in LDS just past the iterate; after the push's barrier, one
+// lane per split row adds the partials in part order (a fixed order) in
+// FP64, so that a row of thousands of arcs is summed no less accurately than
+// a short one, and writes the row.  D starts at half a wave's mean share of
+// the arcs and doubles until the parts fit the spare LDS after the iterate
+// and the first 16 slices; nothing is split when the longest row fits in a
+// wave's mean share.
 
 // One block.  Chooses D, writes the row list after splitting (parts first,
 // tagged with their partial index + 1), one combine entry per split row
