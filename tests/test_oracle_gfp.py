@@ -1,0 +1,248 @@
+"""Pins for the level-l DPPR / Group Forward-Push oracle (no GPU).
+
+Each check ties the oracle to something other than itself: a closed form on
+the complete graph, symmetry and column sums that reversibility forces on an
+undirected graph, the printed first push of the running example, the
+invariant of Lemma lem:fwdpushag evaluated with the exact inverse, the
+stopping rule and error bound of Lemma lem:fpsn-correct, and the truncated
+power series.  A wrong seed (1 / |F| instead of d / |F|), a wrong divisor
+(|F(V_i)| instead of |F(V_j)|), a transposed residue product or a dropped
+(1 - alpha) fails at least one of them."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+ALPHA = 0.15
+
+
+def _pi_d_exact(W):
+    P = O.transition(W)
+    d = O.degrees(W)
+    return O.ppr_closed_form(P, ALPHA) * d[:, None], d
+
+
+def _sbm_case(seed=11, weighted=False, n=60, blocks=4):
+    sizes = synth.equal_blocks(n, blocks)
+    wt = (0.5, 2.0, seed + 1) if weighted else None
+    g = synth.sbm(sizes, 0.35, 0.04, seed, weighted=wt)
+    W = O.weight_matrix(n, g.eu, g.ev, g.weight)
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    leaves = [np.arange(starts[b], starts[b + 1]) for b in range(blocks)]
+    return W, leaves
+
+
+def _ragged_leaves(n, seed):
+    """Leaf sets of unequal sizes that leave some nodes outside S."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n)
+    cuts = [0, 3, 10, 11, 30]
+    return [np.sort(perm[cuts[i]:cuts[i + 1]]) for i in range(len(cuts) - 1)]
+
+
+def _directed_case(seed=21, n=40, p=0.08):
+    """A directed graph (the paper's setting) in which every node has an
+    out-arc (a cycle through all nodes plus random arcs), so pi_d is not
+    symmetric and a transposed operand shows."""
+    rng = np.random.default_rng(seed)
+    src, dst = np.nonzero(rng.random((n, n)) < p)
+    keep = src != dst
+    src = np.concatenate([src[keep], np.arange(n)])
+    dst = np.concatenate([dst[keep], (np.arange(n) + 1) % n])
+    W = O.weight_matrix(n, src, dst, directed=True)
+    W.data[:] = 1.0
+    return W, _ragged_leaves(n, seed)
+
+
+def test_level_dppr_complete_graph_closed_form():
+    # K_n: pi(s,s) = (alpha+beta)/(1+beta), pi(s,t) = beta/(1+beta), d = n-1.
+    n = 9
+    eu, ev = np.triu_indices(n, 1)
+    W = O.weight_matrix(n, eu, ev)
+    pi_d, d = _pi_d_exact(W)
+    beta = (1 - ALPHA) / (n - 1)
+    a = (ALPHA + beta) / (1 + beta)
+    b = beta / (1 + beta)
+    leaves = [np.array([0, 1, 2, 3]), np.array([4, 5]), np.array([6])]
+    L = O.level_dppr(pi_d, leaves)
+    for i, Fi in enumerate(leaves):
+        for j, Fj in enumerate(leaves):
+            if i == j:
+                f = len(Fi)
+                want = (n - 1) * (f * a + f * (f - 1) * b) / (f * f)
+            else:
+                want = (n - 1) * b
+            assert abs(L[i, j] - want) < 1e-12
+
+
+def test_level_dppr_symmetric_and_column_sums():
+    # Undirected: pi_d is symmetric, so the level-l matrix is too; and for
+    # supernodes partitioning V, sum_i |F_i| L[i, j] = mean of d over F_j.
+    for weighted in (False, True):
+        W, leaves = _sbm_case(weighted=weighted)
+        pi_d, d = _pi_d_exact(W)
+        L = O.level_dppr(pi_d, leaves)
+        np.testing.assert_allclose(L, L.T, rtol=1e-10, atol=1e-13)
+        sizes = np.array([len(F) for F in leaves])
+        colsum = (sizes[:, None] * L).sum(axis=0)
+        want = np.array([d[F].mean() for F in leaves])
+        np.testing.assert_allclose(colsum, want, rtol=1e-10)
+
+
+def test_level_dppr_singletons_reduce_to_leaf_dppr():
+    W, _ = _sbm_case(n=20, blocks=2)
+    pi_d, _ = _pi_d_exact(W)
+    idx = [3, 7, 12, 19]
+    L = O.level_dppr(pi_d, [np.array([v]) for v in idx])
+    np.testing.assert_allclose(L, pi_d[np.ix_(idx, idx)], rtol=1e-13)
+
+
+def test_rmax_and_tau():
+    # Eq. eq:rmax with the paper's defaults eps = 1 - 1/e, delta = 1/(10k).
+    k, n, m = 25, 10 ** 6, 3 * 10 ** 7
+    tau = O.tau_default(k, n)
+    assert abs(tau - 2e-4) < 1e-15
+    r = O.rmax_forward(1 - 1 / np.e, 1 / (10 * k), m, tau)
+    assert abs(r - (1 - 1 / np.e) / (10 * k) / (m * 2e-4)) < 1e-20
+
+
+def test_first_push_of_the_running_example(golden_dir):
+    # Section 3.3's example, with the source as a singleton supernode: the
+    # first push turns alpha of d(v0) = 3 into the estimate and sends 0.9 to
+    # each out-neighbour.
+    ex = json.load(open(os.path.join(golden_dir, "push_example.json")))
+    arcs = np.array(ex["second_level"]["arcs"])
+    n = ex["second_level"]["n"]
+    W = O.weight_matrix(n, arcs[:, 0], arcs[:, 1], directed=True)
+    leaves = [np.array([0]), np.array([1]), np.array([2, 3])]
+    a = ex["alpha"]
+    est, r, pushes = O.group_forward_push(W, leaves, 0, a, 1e-9, max_pushes=1)
+    assert pushes == 1
+    assert abs(est[0] - ex["after_first_push"]["estimate_source"]) < 1e-12
+    for v in (1, 2, 3):
+        assert abs(r[v] - ex["after_first_push"]["residue_each_out_neighbour"]) < 1e-12
+    assert est[1] == 0 and est[2] == 0 and r[0] == 0
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_group_forward_push_invariant_every_stop(weighted):
+    # Eq. eq:fwdpushsn-invariant: level-l DPPR = estimate + error term, after
+    # any number of pushes, with pi_d from the exact inverse.
+    W, leaves = _sbm_case(weighted=weighted)
+    n = W.shape[0]
+    leaves = _ragged_leaves(n, 4)
+    pi_d, d = _pi_d_exact(W)
+    L = O.level_dppr(pi_d, leaves)
+    for i in range(len(leaves)):
+        for cap in (0, 1, 7, 60, None):
+            est, r, _ = O.group_forward_push(W, leaves, i, ALPHA, 1e-4, max_pushes=cap)
+            err = O.gfp_error_term(pi_d, leaves, r[None, :], d)[0]
+            np.testing.assert_allclose(est + err, L[i], rtol=1e-11, atol=1e-14)
+
+
+@pytest.mark.parametrize("r_max", [1e-2, 1e-4, 1e-7])
+def test_group_forward_push_stops_within_bound(r_max):
+    # Lemma lem:fpsn-correct: at the stop every r(v) <= d(v) r_max, and the
+    # error term is at most r_max / |F_j| sum_{t in F_j} sum_k pi_d(k, t),
+    # which is r_max * mean_{t in F_j} d(t) on an undirected graph.
+    W, leaves = _sbm_case(seed=12)
+    pi_d, d = _pi_d_exact(W)
+    L = O.level_dppr(pi_d, leaves)
+    bound = r_max * np.array([d[F].mean() for F in leaves])
+    for i in range(len(leaves)):
+        est, r, _ = O.group_forward_push(W, leaves, i, ALPHA, r_max)
+        assert np.all(r <= d * r_max + 1e-18)
+        gap = L[i] - est
+        assert np.all(gap >= -1e-13)
+        assert np.all(gap <= bound * (1 + 1e-9))
+    # the bound is not vacuous: a tiny threshold gives the exact values
+    for i in range(len(leaves)):
+        est, _, _ = O.group_forward_push(W, leaves, i, ALPHA, 1e-15)
+        np.testing.assert_allclose(est, L[i], rtol=1e-10)
+
+
+def test_rounds_with_zero_threshold_are_the_truncated_series():
+    # r_max = 0: every node holding residue pushes in every round, so T rounds
+    # give alpha sum_{t<T} (1-alpha)^t e P^t, the power iteration at T pushes.
+    W, leaves = _sbm_case(seed=13, weighted=True)
+    n = W.shape[0]
+    leaves = _ragged_leaves(n, 5)
+    P = O.transition(W)
+    d = O.degrees(W)
+    for T in (1, 2, 9, 40):
+        ppr, _, _ = O.ppr_power_iteration(P, np.arange(n), ALPHA, fixed_iters=T)
+        want = O.level_dppr(ppr * d[:, None], leaves)
+        est, R, node_est, rounds, _ = O.group_forward_push_rounds(W, leaves, ALPHA, 0.0, T)
+        assert rounds == T
+        np.testing.assert_allclose(est, want, rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("r_max", [1e-3, 1e-6])
+def test_rounds_invariant_stop_and_bound(weighted, r_max):
+    W, leaves = _sbm_case(seed=14, weighted=weighted, n=80, blocks=5)
+    pi_d, d = _pi_d_exact(W)
+    L = O.level_dppr(pi_d, leaves)
+    est, R, node_est, rounds, active = O.group_forward_push_rounds(W, leaves, ALPHA, r_max, 10 ** 5)
+    assert active == 0
+    assert np.all(R <= d[None, :] * r_max + 1e-18)
+    err = O.gfp_error_term(pi_d, leaves, R, d)
+    np.testing.assert_allclose(est + err, L, rtol=1e-11, atol=1e-14)
+    bound = r_max * np.array([d[F].mean() for F in leaves])
+    gap = L - est
+    assert np.all(gap >= -1e-13) and np.all(gap <= bound[None, :] * (1 + 1e-9))
+    # one push at a time and in rounds: both within the same bound of each other
+    for i in range(len(leaves)):
+        seq, _, _ = O.group_forward_push(W, leaves, i, ALPHA, r_max)
+        assert np.all(np.abs(seq - est[i]) <= bound * (1 + 1e-9))
+
+
+def test_rounds_cap_leaves_the_invariant_intact():
+    W, leaves = _sbm_case(seed=15)
+    pi_d, d = _pi_d_exact(W)
+    L = O.level_dppr(pi_d, leaves)
+    for cap in (1, 3):
+        est, R, _, rounds, active = O.group_forward_push_rounds(W, leaves, ALPHA, 1e-8, cap)
+        assert rounds == cap and active > 0
+        err = O.gfp_error_term(pi_d, leaves, R, d)
+        np.testing.assert_allclose(est + err, L, rtol=1e-11, atol=1e-14)
+
+
+@pytest.mark.parametrize("r_max", [1e-3, 1e-12])
+def test_directed_graph_invariant_and_limit(r_max):
+    # On a directed graph pi_d(s, t) != pi_d(t, s): the invariant and the
+    # small-threshold limit check which way every product runs.
+    W, leaves = _directed_case()
+    pi_d, d = _pi_d_exact(W)
+    assert np.abs(pi_d - pi_d.T).max() > 1e-3
+    L = O.level_dppr(pi_d, leaves)
+    assert np.abs(L - L.T).max() > 1e-4
+    est_r, R, _, _, active = O.group_forward_push_rounds(W, leaves, ALPHA, r_max, 10 ** 5)
+    assert active == 0
+    np.testing.assert_allclose(est_r + O.gfp_error_term(pi_d, leaves, R, d), L, rtol=1e-10, atol=1e-14)
+    for i in range(len(leaves)):
+        est, r, _ = O.group_forward_push(W, leaves, i, ALPHA, r_max)
+        err = O.gfp_error_term(pi_d, leaves, r[None, :], d)[0]
+        np.testing.assert_allclose(est + err, L[i], rtol=1e-10, atol=1e-14)
+        if r_max < 1e-9:
+            np.testing.assert_allclose(est, L[i], rtol=1e-8)
+
+
+def test_rounds_stop_with_isolated_nodes():
+    # An isolated node never holds residue; the strict test r > d r_max (with
+    # d = 0) keeps it idle, so the rounds end on their own.
+    n = 50
+    g = synth.sbm(synth.equal_blocks(n, 2), 0.4, 0.05, 16)
+    keep = (g.eu < n - 2) & (g.ev < n - 2)  # nodes n-2, n-1 isolated
+    W = O.weight_matrix(n, g.eu[keep], g.ev[keep])
+    leaves = [np.arange(0, 20), np.arange(20, n)]  # the second holds both isolated nodes
+    est, R, _, rounds, active = O.group_forward_push_rounds(W, leaves, ALPHA, 1e-5, 10 ** 4)
+    assert active == 0 and rounds < 10 ** 4
+    assert np.all(R[:, n - 2:] == 0)
+    pi_d, d = _pi_d_exact(W)
+    L = O.level_dppr(pi_d, leaves)
+    np.testing.assert_allclose(est + O.gfp_error_term(pi_d, leaves, R, d), L, rtol=1e-10, atol=1e-14)
