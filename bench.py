@@ -199,7 +199,50 @@ def spmm_large(ops, dev, n=1_000_000, gamma=2.2, avg_degree=30, n_src=4096, tol=
                          f"L1 {tol:g} (T={T}), DPPR among the sources, whole ppr_matrix call",
                 kernel="stream_step_kernel", ms=best, bound="hbm", unit="GB/s",
                 achieved=alg / (best * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
-                frac=alg / (best * 1e-3) / 1e9 / PEAK_HBM_GBS, work=f"{alg:.4g} B over {T - 1} pushes", nnz=nnz)
+                frac=alg / (best * 1e-3) / 1e9 / PEAK_HBM_GBS, work=f"{alg:.4g} B over {T - 1} pushes",
+                nnz=nnz), (g, csr)
+
+
+def gfp_level(ops, dev, g, csr, k=25, reps=3):
+    """Level-l DPPR among the k = 25 children of the top supernode of the
+    10^6-node Chung-Lu graph above, by Group Forward-Push in rounds (one
+    gfp_level_dppr call from all 25 source supernodes).  The children
+    partition V into contiguous id ranges (the hierarchy itself is not built
+    here).  Threshold by Eq. eq:rmax with the paper's defaults
+    eps = 1 - 1/e, delta = 1/(10k), tau = 1/sqrt(kn), m = nnz.
+    Algorithmic bytes per round (gfp_round_kernel): 16 n ld (what the last
+    round sent, read once; the residue read and written; what this round
+    sends, written; ld = 32 columns) + 4 nnz + 24 n (arcs, row table,
+    degrees)."""
+    import torch
+    import synth
+
+    n = g.n
+    nnz = int(g.col_idx.shape[0])
+    sizes = synth.equal_blocks(n, k)
+    ptr = torch.as_tensor(np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32), device=dev)
+    idx = torch.arange(n, dtype=torch.int32, device=dev)
+    eps, delta, tau = 1.0 - 1.0 / math.e, 1.0 / (10 * k), 1.0 / math.sqrt(k * n)
+    r_max = eps * delta / (nnz * tau)
+    best = None
+    rounds = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out, _, _, rounds, _ = ops.gfp_level_dppr(csr, (ptr, idx), ALPHA, r_max, 10000)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+    ld = 32 * ((k + 31) // 32)
+    alg = rounds * (16.0 * n * ld + 4.0 * nnz + 24.0 * n)
+    return dict(workload=f"chung_lu n={n} gamma=2.2 mean degree 30, k={k} supernodes partitioning V, "
+                         f"r_max={r_max:.3e} (eps 1-1/e, delta 1/(10k), tau 1/sqrt(kn)), whole gfp_level_dppr call",
+                kernel="gfp_round_kernel", ms=best, rounds=rounds, bound="hbm", unit="GB/s",
+                achieved=alg / (best * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
+                frac=alg / (best * 1e-3) / 1e9 / PEAK_HBM_GBS, work=f"{alg:.4g} B over {rounds} rounds")
 
 
 def counters_pass(ops, b, x0, dev):
@@ -232,6 +275,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the stage-timing pass")
     ap.add_argument("--no-spmm", action="store_true", help="skip the all-pairs SpMM measurement (n = 20000)")
+    ap.add_argument("--no-gfp", action="store_true",
+                    help="skip the level-l DPPR (group forward push) leg on the 10^6-node graph")
     ap.add_argument("--no-spmm-large", action="store_true",
                     help="skip the 4096-source SpMM on the n = 10^6 graph")
     ap.add_argument("--counters", action="store_true",
@@ -371,13 +416,20 @@ def main():
         log(f"all-pairs SpMM (n = 20000): {spmm['ms']:.1f} ms, {spmm['achieved']:.0f} GB/s algorithmic")
 
     spmm_big = None
+    gfp = None
     if not args.no_spmm_large:
         del bufs
         plan.close()
         plan = None
         torch.cuda.empty_cache()
-        spmm_big = spmm_large(ops, dev)
+        spmm_big, (g_big, csr_big) = spmm_large(ops, dev)
         log(f"4096-source SpMM (n = 10^6): {spmm_big['ms']:.1f} ms, {spmm_big['achieved']:.0f} GB/s algorithmic")
+        if not args.no_gfp:
+            torch.cuda.empty_cache()
+            gfp = gfp_level(ops, dev, g_big, csr_big)
+            log(f"level-l DPPR by group forward push (n = 10^6, k = 25): {gfp['ms']:.2f} ms, "
+                f"{gfp['rounds']} rounds, {gfp['achieved']:.0f} GB/s algorithmic")
+        del g_big, csr_big
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -409,6 +461,7 @@ def main():
         "stages": stages,
         "spmm": spmm,
         "spmm_large": spmm_big,
+        "level_dppr_gfp": gfp,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -118,6 +118,58 @@ ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src,
                       void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Level-l DPPR by Group Forward-Push (Section 3.2 Definition def:spprdeg;
+ * Section 4.2 Algorithm alg:fwdpushsn, Eq. eq:rmax)
+ * ---------------------------------------------------------------------- */
+
+/* Workspace bytes needed by gfp_level_dppr. */
+size_t gfp_workspace(const ppr_csr* g, int32_t k, int32_t max_rounds);
+
+/*
+ * Approximate level-l DPPR between the k children V_0 .. V_{k-1} of a
+ * supernode, from all k source supernodes at once.
+ *
+ * Supernode V_i is its leaf set F(V_i) = leaf_idx[leaf_ptr[i] .. leaf_ptr[i+1]):
+ *  leaf_ptr  device int32[k+1], leaf_ptr[0] = 0, leaf_ptr[k] = n_leaves, each
+ *            set holding 1 .. n entries;
+ *  leaf_idx  device int32[n_leaves], node ids in [0, n).  The sets need not
+ *            cover the graph; a node listed twice counts twice.
+ * The leaf lists are checked on the device before any other work (this
+ * synchronizes `stream`); invalid lists give PPR_EINVAL with no output
+ * written.
+ *
+ * Residue r_i(v) starts at d(v) / |F(V_i)| on the leaves of V_i.  The pushes
+ * of Algorithm alg:fwdpushsn run in synchronous rounds: in each round every
+ * (source i, node v) pair with r_i(v) > d(v) * r_max adds alpha * r_i(v) to
+ * its estimate e_i(v), sends (1 - alpha) r_i(v) w_vu / d(v) to each
+ * neighbour u (received in the next round) and keeps 0.  The rounds stop
+ * after the first round in which no pair pushed, or after max_rounds rounds
+ * (then what the last round sent is delivered to the residues and the call
+ * returns PPR_ENOCONV with every output written).  r_max = 0 pushes every
+ * nonzero residue each round: max_rounds rounds are then the power series
+ * truncated at max_rounds terms.  The paper's threshold is
+ * r_max = eps * delta / (m * tau), tau = 1 / sqrt(k n) (Eq. eq:rmax).
+ *
+ *  dppr_out  float[k * k]: dppr_out[i*k + j] = sum over v in F(V_j) of
+ *            e_i(v) / |F(V_j)|, the estimate of pi_d(V_i, V_j).  The FP32
+ *            estimates are summed in FP64.
+ *  est_out   float[k * n] or NULL: e_i(v) at [i*n + v].
+ *  resid_out float[k * n] or NULL: r_i(v) at [i*n + v] when the rounds end.
+ *            With est_out it satisfies Eq. eq:fwdpushsn-invariant; after a
+ *            normal stop every r_i(v) <= d(v) * r_max, and then
+ *            0 <= pi_d(V_i, V_j) - dppr_out[i*k+j] <= r_max * (mean degree
+ *            of F(V_j)) up to FP32 rounding (Lemma lem:fpsn-correct).
+ *  rounds_out HOST int32 or NULL: rounds run (including the last, empty one).
+ * The call synchronizes `stream` every few rounds to read the push count.
+ * Returns PPR_EINVAL for alpha outside (0,1), r_max < 0 or non-finite,
+ * max_rounds < 1, k < 1 or NULL arrays; PPR_EUNSUPPORTED for n >= 2^24.
+ */
+ppr_status gfp_level_dppr(const ppr_csr* g, const int32_t* leaf_ptr, const int32_t* leaf_idx,
+                          int32_t k, int64_t n_leaves, float alpha, double r_max,
+                          int32_t max_rounds, float* dppr_out, float* est_out, float* resid_out,
+                          int32_t* rounds_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * PDist (Definition def:pprdist, Eq. eq:pprdist)
  * ---------------------------------------------------------------------- */
 

@@ -164,13 +164,51 @@ __device__ __forceinline__ float4 slab_load(__amdgpu_buffer_rsrc_t r, uint32_t o
     return make_float4(__int_as_float(v[0]), __int_as_float(v[1]), __int_as_float(v[2]), __int_as_float(v[3]));
 }
 
+// Sum over the arcs of this lane's row of w_vu * Y[u][4 columns of piece
+// qoff] (w = 1 without weights).  The 8 lanes of a row read 8 arc indices at
+// once, coalesced, and pass them round with ds_bpermute; each lane then adds
+// its row's neighbours in arc order, so a row's sum does not depend on which
+// rows share its wave.  Every lane of the wave must call it (dg = 0 for a
+// lane without a row).
+template <bool WEIGHTED>
+__device__ __forceinline__ float4 slab_gather(__amdgpu_buffer_rsrc_t rin, const int32_t* __restrict__ col_idx,
+                                              const float* __restrict__ weight, int rs, int dg, int lane,
+                                              uint32_t qoff) {
+    const int q = lane % kSlabVec;
+    int dmax = dg;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, kWave));
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int lead = (lane & ~(kSlabVec - 1)) * 4;  // ds_bpermute address of the group's first lane
+    for (int k0 = 0; k0 < dmax; k0 += kSlabVec) {
+        const bool ok = k0 + q < dg;
+        const int idx = ok ? col_idx[rs + k0 + q] : -1;
+        float wl = 0.f;
+        if (WEIGHTED) wl = ok ? weight[rs + k0 + q] : 0.f;
+        float4 y[kSlabVec];
+#pragma unroll
+        for (int j = 0; j < kSlabVec; ++j) {
+            const int u = __builtin_amdgcn_ds_bpermute(lead + 4 * j, idx);
+            y[j] = slab_load(rin, ((uint32_t)u << 7) | qoff);
+        }
+#pragma unroll
+        for (int j = 0; j < kSlabVec; ++j) {
+            if (WEIGHTED) {
+                const float w = __int_as_float(__builtin_amdgcn_ds_bpermute(lead + 4 * j, __float_as_int(wl)));
+                f4_fma(acc, w, y[j]);
+            } else {
+                f4_acc(acc, y[j]);
+            }
+        }
+    }
+    return acc;
+}
+
 // One push (MODE 0: forward, forcing alpha at each column's source row;
 // MODE 1: adjoint, forcing deg[v] * G[v][col]).  A wave takes 8 rows of the
 // degree order side by side within one slab: lane = 8 * g + q, where g picks
-// the row and q 4 of the slab's 32 columns (one 16-byte load per arc).  The
-// group's lanes read 8 arc indices at once, coalesced, and pass them round
-// with ds_bpermute; each lane then sums its row's neighbours in arc order,
-// so a row's result does not depend on which rows share its wave.
+// the row and q 4 of the slab's 32 columns (one 16-byte load per arc, summed
+// by slab_gather).
 template <int MODE, bool WEIGHTED, bool FINAL>
 __global__ __launch_bounds__(256) void stream_step_kernel(
     const RowEnt* __restrict__ rows, const int32_t* __restrict__ col_idx,
@@ -195,34 +233,9 @@ __global__ __launch_bounds__(256) void stream_step_kernel(
         dg = e.re - e.rs;
         v = e.v;
     }
-    int dmax = dg;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, kWave));
     const uint32_t qoff = (uint32_t)q * 16u;
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 acc = slab_gather<WEIGHTED>(rin, col_idx, weight, rs, dg, lane, qoff);
     if (has_row && dg == 0) acc = slab_load(rin, ((uint32_t)v << 7) | qoff);
-    const int lead = (lane & ~(kSlabVec - 1)) * 4;  // ds_bpermute address of the group's first lane
-    for (int k0 = 0; k0 < dmax; k0 += kSlabVec) {
-        const bool ok = k0 + q < dg;
-        const int idx = ok ? col_idx[rs + k0 + q] : -1;
-        float wl = 0.f;
-        if (WEIGHTED) wl = ok ? weight[rs + k0 + q] : 0.f;
-        float4 y[kSlabVec];
-#pragma unroll
-        for (int j = 0; j < kSlabVec; ++j) {
-            const int u = __builtin_amdgcn_ds_bpermute(lead + 4 * j, idx);
-            y[j] = slab_load(rin, ((uint32_t)u << 7) | qoff);
-        }
-#pragma unroll
-        for (int j = 0; j < kSlabVec; ++j) {
-            if (WEIGHTED) {
-                const float w = __int_as_float(__builtin_amdgcn_ds_bpermute(lead + 4 * j, __float_as_int(wl)));
-                f4_fma(acc, w, y[j]);
-            } else {
-                f4_acc(acc, y[j]);
-            }
-        }
-    }
     if (!has_row) return;
     const int col0 = slab * kSlab + q * 4;
     float x[4] = {acc.x, acc.y, acc.z, acc.w};

@@ -93,6 +93,36 @@ def ppr_matrix(g: Csr, src, tgt=None, alpha=0.15, tol=1e-6, max_iter=100000, wan
     return ppr, dppr, iters.value, (resid[:n_src] if resid is not None else None)
 
 
+def gfp_level_dppr(g: Csr, leaves, alpha=0.15, r_max=0.0, max_rounds=10000, want_est=False, want_resid=False,
+                   allow_noconv=False):
+    """Level-l DPPR between supernodes by Group Forward-Push in rounds.
+    ``leaves`` is a list of k node-id arrays (the leaf sets) or a pair
+    (leaf_ptr, leaf_idx).  Returns (dppr [k, k], est [k, n] or None,
+    resid [k, n] or None, rounds, status)."""
+    dev = g.row_ptr.device
+    if isinstance(leaves, tuple):
+        ptr, idx = leaves
+    else:
+        sizes = [len(F) for F in leaves]
+        ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+        idx = np.concatenate([np.asarray(F, dtype=np.int32) for F in leaves]) if leaves else np.zeros(0, np.int32)
+    ptr = torch.as_tensor(ptr, dtype=torch.int32, device=dev).contiguous()
+    idx = torch.as_tensor(idx, dtype=torch.int32, device=dev).contiguous()
+    k = int(ptr.numel()) - 1
+    cg = g.c()
+    ws = _ws(L.lib().gfp_workspace(C.byref(cg), k, max_rounds), dev)
+    out = torch.empty((k, k), dtype=torch.float32, device=dev)
+    est = torch.empty((k, g.n), dtype=torch.float32, device=dev) if want_est else None
+    resid = torch.empty((k, g.n), dtype=torch.float32, device=dev) if want_resid else None
+    rounds = C.c_int32()
+    st = L.lib().gfp_level_dppr(C.byref(cg), _ptr(ptr), _ptr(idx), k, int(idx.numel()), alpha, r_max, max_rounds,
+                                _ptr(out), _ptr(est), _ptr(resid), C.byref(rounds), _ptr(ws), ws.numel(),
+                                _stream(dev))
+    allow = (L.PPR_OK, L.PPR_ENOCONV) if allow_noconv else (L.PPR_OK,)
+    L.check("gfp_level_dppr", st, allow)
+    return out, est, resid, rounds.value, st
+
+
 def pdist(dppr: torch.Tensor, n_clamp: int):
     _require_cuda(dppr)
     k = dppr.shape[0]

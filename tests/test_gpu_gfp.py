@@ -1,0 +1,199 @@
+"""GPU parity: level-l DPPR by Group Forward-Push in rounds (gfp_level_dppr),
+through the C ABI, against the FP64 oracle.
+
+With r_max = 0 the rounds are the truncated power series, a unique result,
+compared element by element.  With r_max > 0 the order of pushes is free
+(several results are correct), so the GPU result is checked for what defines
+a valid one: the invariant of Lemma lem:fwdpushag with the exact inverse,
+the stopping rule, the error bound of Lemma lem:fpsn-correct, and (at any
+size) conservation of residue plus estimate."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from gpu_util import ALPHA, get_ops
+
+pytestmark = pytest.mark.gpu
+
+REL = 2e-5   # FP32 rounds against FP64, relative to the largest value
+
+
+@pytest.fixture(scope="module")
+def ops():
+    return get_ops()
+
+
+def _blocks(sizes):
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    return [np.arange(starts[b], starts[b + 1]) for b in range(len(sizes))]
+
+
+def _ragged(n, k, seed):
+    """k leaf sets of ragged sizes (1 .. 2n/k) over a random part of V."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n)
+    sizes = rng.integers(1, max(2, 2 * n // k), size=k)
+    sizes = np.minimum(sizes, n // k)
+    sizes[0] = 1
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    return [np.sort(perm[starts[i]:starts[i + 1]]) for i in range(k)]
+
+
+def _case(n, blocks, weighted, seed):
+    wt = (0.5, 2.0, seed + 1) if weighted else None
+    sizes = synth.equal_blocks(n, blocks)
+    g = synth.sbm(sizes, min(1.0, 12.0 / (n / blocks)), 2.0 / n, seed, weighted=wt)
+    return g, _blocks(sizes)
+
+
+def _exact(g):
+    W = O.weight_matrix(g.n, g.eu, g.ev, g.weight)
+    d = O.degrees(W)
+    return W, O.ppr_closed_form(O.transition(W), ALPHA) * d[:, None], d
+
+
+@pytest.mark.parametrize("n,blocks,k_ragged,weighted", [(600, 6, 0, False), (601, 5, 40, True), (97, 3, 0, False)])
+def test_zero_threshold_is_the_truncated_series(ops, n, blocks, k_ragged, weighted):
+    g, leaves = _case(n, blocks, weighted, synth.BASE_SEED + n)
+    if k_ragged:
+        leaves = _ragged(n, k_ragged, synth.BASE_SEED + 3)  # two slabs of columns
+    W = O.weight_matrix(g.n, g.eu, g.ev, g.weight)
+    d = O.degrees(W)
+    P = O.transition(W)
+    csr = ops.Csr.from_graph(g, "cuda")
+    for T in (1, 2, 17, 86):
+        print(f"[gfp zero] n={n} k={len(leaves)} T={T}", flush=True)
+        out, est, resid, rounds, st = ops.gfp_level_dppr(csr, leaves, ALPHA, 0.0, T, want_est=True,
+                                                          want_resid=True, allow_noconv=True)
+        assert rounds == T
+        ppr, _, _ = O.ppr_power_iteration(P, np.arange(n), ALPHA, fixed_iters=T)
+        want = O.level_dppr(ppr * d[:, None], leaves)
+        got = out.double().cpu().numpy()
+        assert np.abs(got - want).max() <= REL * np.abs(want).max()
+        e_o, R_o, ne_o, r_o, _ = O.group_forward_push_rounds(W, leaves, ALPHA, 0.0, T)
+        assert np.abs(est.double().cpu().numpy() - ne_o).max() <= REL * np.abs(ne_o).max()
+        assert np.abs(resid.double().cpu().numpy() - R_o).max() <= REL * max(np.abs(R_o).max(), 1e-30)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("r_max", [1e-3, 1e-5, 1e-7])
+def test_threshold_result_is_valid(ops, weighted, r_max):
+    g, leaves = _case(1500, 8, weighted, synth.BASE_SEED + 17)
+    W, pi_d, d = _exact(g)
+    L = O.level_dppr(pi_d, leaves)
+    csr = ops.Csr.from_graph(g, "cuda")
+    print(f"[gfp valid] weighted={weighted} r_max={r_max}", flush=True)
+    out, est, resid, rounds, st = ops.gfp_level_dppr(csr, leaves, ALPHA, r_max, 10000, want_est=True,
+                                                      want_resid=True)
+    got = out.double().cpu().numpy()
+    R = resid.double().cpu().numpy()
+    E = est.double().cpu().numpy()
+    # stopping rule (the GPU takes it in FP32)
+    assert np.all(R <= d[None, :] * r_max * (1 + 1e-5))
+    # the k x k output aggregates the per-node estimates
+    agg = np.stack([E[:, F].sum(axis=1) / len(F) for F in leaves], axis=1)
+    assert np.abs(got - agg).max() <= 1e-6 * np.abs(agg).max()
+    # invariant: estimate + error term = exact level-l DPPR
+    err = O.gfp_error_term(pi_d, leaves, R, d)
+    assert np.abs(got + err - L).max() <= REL * np.abs(L).max()
+    # error bound of Lemma lem:fpsn-correct (undirected: r_max * mean degree)
+    bound = r_max * np.array([d[F].mean() for F in leaves])
+    gap = L - got
+    tol = REL * np.abs(L).max()
+    assert np.all(gap >= -tol) and np.all(gap <= bound[None, :] + tol)
+    # the FP64 rounds oracle lands within the same bound
+    e_o, _, _, _, _ = O.group_forward_push_rounds(W, leaves, ALPHA, r_max, 10000)
+    assert np.all(np.abs(got - e_o) <= bound[None, :] + tol)
+
+
+def test_round_cap_keeps_the_invariant(ops):
+    g, leaves = _case(700, 4, False, synth.BASE_SEED + 23)
+    W, pi_d, d = _exact(g)
+    L = O.level_dppr(pi_d, leaves)
+    csr = ops.Csr.from_graph(g, "cuda")
+    for cap in (1, 3):
+        print(f"[gfp cap] cap={cap}", flush=True)
+        out, est, resid, rounds, st = ops.gfp_level_dppr(csr, leaves, ALPHA, 1e-9, cap, want_resid=True,
+                                                          allow_noconv=True)
+        from paper_2112_14944_amd import _lib
+        assert st == _lib.PPR_ENOCONV and rounds == cap
+        err = O.gfp_error_term(pi_d, leaves, resid.double().cpu().numpy(), d)
+        assert np.abs(out.double().cpu().numpy() + err - L).max() <= REL * np.abs(L).max()
+        e_o, R_o, _, _, _ = O.group_forward_push_rounds(W, leaves, ALPHA, 1e-9, cap)
+        assert np.abs(out.double().cpu().numpy() - e_o).max() <= REL * np.abs(e_o).max()
+
+
+def test_isolated_leaves_and_outside_nodes(ops):
+    # isolated nodes in a leaf set start with zero residue; nodes outside S
+    # carry residue but contribute no estimate
+    n = 300
+    g0, _ = _case(n, 3, False, synth.BASE_SEED + 29)
+    keep = (g0.eu < n - 5) & (g0.ev < n - 5)
+    g = synth.build_graph(n, g0.eu[keep], g0.ev[keep])
+    leaves = [np.arange(0, 50), np.arange(100, 140), np.arange(n - 10, n)]
+    W, pi_d, d = _exact(g)
+    L = O.level_dppr(pi_d, leaves)
+    csr = ops.Csr.from_graph(g, "cuda")
+    out, est, resid, rounds, st = ops.gfp_level_dppr(csr, leaves, ALPHA, 1e-6, 10000, want_resid=True)
+    R = resid.double().cpu().numpy()
+    assert np.all(R[:, n - 5:] == 0)
+    got = out.double().cpu().numpy()
+    err = O.gfp_error_term(pi_d, leaves, R, d)
+    assert np.abs(got + err - L).max() <= REL * np.abs(L).max()
+
+
+def test_invalid_leaf_lists_are_rejected(ops):
+    from paper_2112_14944_amd import _lib
+    g, _ = _case(200, 2, False, synth.BASE_SEED + 31)
+    csr = ops.Csr.from_graph(g, "cuda")
+    bad = [
+        (np.array([0, 3, 3], np.int32), np.array([1, 2, 3], np.int32)),        # empty set
+        (np.array([0, 2, 3], np.int32), np.array([1, 200, 3], np.int32)),      # id out of range
+        (np.array([0, 2, 3], np.int32), np.array([1, -1, 3], np.int32)),       # negative id
+        (np.array([1, 2, 3], np.int32), np.array([1, 2, 3], np.int32)),        # leaf_ptr[0] != 0
+        (np.array([0, 3, 2, 3], np.int32), np.array([1, 2, 3], np.int32)),     # decreasing
+    ]
+    for ptr, idx in bad:
+        with pytest.raises(_lib.PprvizError) as ei:
+            ops.gfp_level_dppr(csr, (ptr, idx), ALPHA, 1e-6, 100)
+        assert ei.value.status == _lib.PPR_EINVAL
+
+
+def test_full_size_partition_of_a_million_nodes(ops):
+    # Chung-Lu n = 10^6, exponent 2.2, mean degree 30; 25 supernodes that
+    # partition V into contiguous id ranges (standing in for the top level of
+    # a hierarchy); the paper's defaults eps = 1 - 1/e, delta = 1/(10k),
+    # tau = 1/sqrt(kn) give r_max by Eq. eq:rmax, with m = nnz.
+    n, k = 1_000_000, 25
+    g = synth.chung_lu(n, 2.2, 30, synth.BASE_SEED + 4)
+    leaves = _blocks(synth.equal_blocks(n, k))
+    r_max = O.rmax_forward(1 - 1 / np.e, 1 / (10 * k), g.nnz, O.tau_default(k, n))
+    print(f"[gfp full] n={n} nnz={g.nnz} k={k} r_max={r_max:.3e}", flush=True)
+    csr = ops.Csr.from_graph(g, "cuda")
+    out, est, resid, rounds, st = ops.gfp_level_dppr(csr, leaves, ALPHA, r_max, 10000, want_est=True,
+                                                      want_resid=True)
+    torch.cuda.synchronize()
+    print(f"[gfp full] rounds={rounds}", flush=True)
+    W = O.weight_matrix(n, g.eu, g.ev)
+    d = O.degrees(W)
+    R = resid.double().cpu().numpy()
+    E = est.double().cpu().numpy()
+    got = out.double().cpu().numpy()
+    # stopping rule and conservation: each push moves alpha r into the
+    # estimate and (1 - alpha) r to the neighbours, so residue + estimate
+    # keeps the seeds' total mean degree of F(V_i)
+    assert np.all(R <= d[None, :] * r_max * (1 + 1e-5))
+    mass = R.sum(axis=1) + E.sum(axis=1)
+    want_mass = np.array([d[F].mean() for F in leaves])
+    assert np.abs(mass - want_mass).max() <= 1e-4 * want_mass.max()
+    # against the FP64 rounds oracle: both stop within the error bound
+    e_o, R_o, _, rounds_o, _ = O.group_forward_push_rounds(W, leaves, ALPHA, r_max, 10000)
+    print(f"[gfp full] oracle rounds={rounds_o}", flush=True)
+    bound = r_max * np.array([d[F].mean() for F in leaves])
+    tol = 1e-5 * np.abs(e_o).max()
+    assert np.all(np.abs(got - e_o) <= bound[None, :] + tol)
+    # an undirected graph's exact level-l DPPR is symmetric: the estimate is
+    # within the bound of being so
+    assert np.all(np.abs(got - got.T) <= np.maximum(bound[None, :], bound[:, None]) + tol)
