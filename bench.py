@@ -279,6 +279,8 @@ def main():
                     help="skip the level-l DPPR (group forward push) leg on the 10^6-node graph")
     ap.add_argument("--no-spmm-large", action="store_true",
                     help="skip the 4096-source SpMM on the n = 10^6 graph")
+    ap.add_argument("--only-gfp", action="store_true",
+                    help="run only the level-l DPPR leg (10^6-node graph) and print its JSON object")
     ap.add_argument("--counters", action="store_true",
                     help="one eager batched pass plus a 1 GiB calibration copy (for rocprofv3 --pmc), no timing")
     args = ap.parse_args()
@@ -295,6 +297,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
+    if args.only_gfp:
+        g_big = synth.chung_lu(1_000_000, 2.2, 30, synth.BASE_SEED + 4)
+        gfp = gfp_level(ops, dev, g_big, ops.Csr.from_graph(g_big, dev))
+        log(f"level-l DPPR by group forward push (n = 10^6, k = 25): {gfp['ms']:.2f} ms, "
+            f"{gfp['rounds']} rounds, {gfp['achieved']:.0f} GB/s algorithmic")
+        print(json.dumps({"level_dppr_gfp": gfp}), flush=True)
+        return
     G = args.graphs
     t0 = time.perf_counter()
     graphs = synth.sbm_batch(G, seed=synth.BASE_SEED)

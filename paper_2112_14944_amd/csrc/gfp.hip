@@ -17,9 +17,12 @@
 // The round is the streaming power-iteration step with a thresholded
 // epilogue: iterate columns in slabs of 32 (node-major within a slab), rows
 // by degree, 8 rows side by side per wave, neighbour rows gathered as 128-byte
-// pieces.  Round t counts its pushes in a device counter; round t + 1 exits at
-// once when round t pushed nothing, and the host reads the counter every few
-// rounds to stop launching.
+// pieces.  Each round flags, per slab and node, the rows that pushed, and the
+// next round reads only flagged neighbours and skips rows that received
+// nothing, so the late rounds, in which few pairs still push, cost little
+// more than reading the arcs.  Round t sets a device flag when it pushed
+// anything; round t + 1 exits at once when round t pushed nothing, and the
+// host reads the flag every few rounds to stop launching.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -31,7 +34,13 @@ namespace pprviz {
 namespace {
 
 constexpr int kGfpChunk = 2048;  // leaves per block of the aggregation
-constexpr int kGfpInfo = 4;      // check results: [0] bad flag, [1] largest leaf set
+constexpr int kGfpInfo = 4;      // [0] bad leaf lists, [1] largest leaf set, [2] wide rows
+// Rows with more arcs than this are gathered by a whole wave (8 lane groups
+// on one row) instead of one 8-lane group: the longest row then takes 64
+// arcs per pass instead of 8, which keeps it from outlasting the rest of a
+// round.
+constexpr int kGfpWideDeg = 256;
+static_assert(kGfpWideDeg + 2 <= kDegKeys, "wide rows must have degree classes of their own");
 
 struct GfpWs {
     RowEnt* rows;
@@ -41,7 +50,8 @@ struct GfpWs {
     float* resid;      // residue kept by each (node, column), slab layout
     float* est;        // estimate per (node, column), slab layout
     float* send[2];    // r / d of the pairs that pushed, by round parity
-    int32_t* active;   // pushes per round
+    uint8_t* flag[2];  // per slab and node: pushed in that round, by round parity
+    int32_t* active;   // 1 when the round pushed anything
     int32_t* info;
     double* part;      // aggregation partials [k][chunks][ld]
 };
@@ -61,6 +71,8 @@ void gfp_ws_layout(Cursor& c, int32_t n, int32_t k, int32_t max_rounds, GfpWs* w
     t.est = c.template take<float>((size_t)(n * ld));
     t.send[0] = c.template take<float>((size_t)(n * ld));
     t.send[1] = c.template take<float>((size_t)(n * ld));
+    t.flag[0] = c.template take<uint8_t>((size_t)(n * (ld / kSlab)));
+    t.flag[1] = c.template take<uint8_t>((size_t)(n * (ld / kSlab)));
     t.active = c.template take<int32_t>((size_t)std::max(max_rounds, 1));
     t.info = c.template take<int32_t>(kGfpInfo);
     t.part = c.template take<double>((size_t)(k * gfp_chunks(n) * ld));
@@ -97,6 +109,13 @@ __global__ void gfp_check_idx_kernel(const int32_t* __restrict__ leaf_idx, int64
     }
 }
 
+// Rows with more than kGfpWideDeg arcs: after the scatter of the degree
+// order, hist[c] is the end of class c (classes run from the largest degree
+// down), so the end of the class of degree kGfpWideDeg + 1 counts them.
+__global__ void gfp_wide_count_kernel(const int32_t* __restrict__ hist, int32_t* __restrict__ info) {
+    info[2] = hist[kDegKeys - 2 - kGfpWideDeg];
+}
+
 // Initial residues: d(v) / |F(V_i)| in column i at each leaf v of V_i.  A
 // leaf listed twice in one set receives its share twice.
 __global__ void gfp_seed_kernel(const int32_t* __restrict__ leaf_ptr, const int32_t* __restrict__ leaf_idx,
@@ -120,16 +139,23 @@ struct GfpRound {
     float* est;
     const float* send_in;   // what the previous round pushed (GATHER)
     float* send_out;        // what this round pushes (SELECT)
-    int32_t* active;        // active[t] counts this round's pushes
+    const uint8_t* flag_in; // which nodes pushed in the previous round, per slab (GATHER)
+    uint8_t* flag_out;      // which nodes push in this round, per slab (SELECT)
+    int32_t* active;        // active[t] = 1 when round t pushed anything
     int32_t n;
+    int32_t wide;           // rows 0 .. wide-1 of the degree order have > kGfpWideDeg arcs
+    int32_t wide_blocks;    // blocks of 4 wide rows (one per wave), ahead of the rest
     float alpha;
     float r_max;
     int32_t t;
 };
 
 // One round.  GATHER: add (1 - alpha) sum_u w_vu send_in[u] to the kept
-// residue (rounds t >= 1, and the closing delivery after a round cap).
-// SELECT: push every pair over its threshold (rounds t >= 0).
+// residue (rounds t >= 1, and the closing delivery after a round cap),
+// reading only neighbours flagged as having pushed; a row with no such
+// neighbour keeps its residue, which the previous round left at or below
+// its threshold, and is skipped.  SELECT: push every pair over its
+// threshold (rounds t >= 0) and flag the rows that pushed.
 template <bool WEIGHTED, bool GATHER, bool SELECT>
 __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid grid) {
     if (a.t > 0 && a.active[a.t - 1] == 0) return;  // the previous round pushed nothing
@@ -140,8 +166,11 @@ __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid g
     stream_block_map(grid, slab, rb);
     const int n = a.n;
     const int64_t slab_off = (int64_t)slab * n * kSlab;
-    const int ri = rb * kStreamRowsPerBlock + wave * kStreamRowsPerWave + lane / kSlabVec;
-    const bool has_row = ri < n;
+    const int grp = lane / kSlabVec;
+    const bool wide = rb < a.wide_blocks;  // uniform in the block
+    const int ri = wide ? rb * 4 + wave
+                        : a.wide + (rb - a.wide_blocks) * kStreamRowsPerBlock + wave * kStreamRowsPerWave + grp;
+    const bool has_row = ri < (wide ? a.wide : n);
     int rs = 0, dg = 0, v = 0;
     if (has_row) {
         const RowEnt e = load_row(as_global(a.rows), ri);
@@ -150,15 +179,35 @@ __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid g
         v = e.v;
     }
     const uint32_t qoff = (uint32_t)q * 16u;
+    const int64_t flag_off = (int64_t)slab * n;
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    int got = 1;
     if (GATHER) {
         const uint32_t slab_bytes = (uint32_t)n * (kSlab * 4);
         const __amdgpu_buffer_rsrc_t rin = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float*>(a.send_in + slab_off), 0, (int)slab_bytes, 0x00020000);
-        acc = slab_gather<WEIGHTED>(rin, a.col_idx, a.weight, rs, dg, lane, qoff);
+        if (wide) {
+            acc = slab_gather<WEIGHTED, true, kWave>(rin, a.col_idx, a.weight, rs + kSlabVec * grp,
+                                                     max(dg - kSlabVec * grp, 0), lane, qoff,
+                                                     a.flag_in + flag_off, &got);
+            // add the 8 groups' sums (a fixed tree) into every group
+#pragma unroll
+            for (int o = kSlabVec; o < kWave; o <<= 1) {
+                acc.x += __shfl_xor(acc.x, o, kWave);
+                acc.y += __shfl_xor(acc.y, o, kWave);
+                acc.z += __shfl_xor(acc.z, o, kWave);
+                acc.w += __shfl_xor(acc.w, o, kWave);
+                got |= __shfl_xor(got, o, kWave);
+            }
+        } else {
+            acc = slab_gather<WEIGHTED, true>(rin, a.col_idx, a.weight, rs, dg, lane, qoff, a.flag_in + flag_off,
+                                              &got);
+        }
     }
+    // a wide row is finished by its first lane group
+    const bool owner = has_row && (!wide || grp == 0);
     int pushed = 0;
-    if (has_row) {
+    if (owner && got) {
         const int64_t off = slab_off + (int64_t)v * kSlab + q * 4;
         float4* r4 = reinterpret_cast<float4*>(a.resid + off);
         float r[4] = {r4->x, r4->y, r4->z, r4->w};
@@ -195,9 +244,17 @@ __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid g
         *r4 = make_float4(r[0], r[1], r[2], r[3]);
     }
     if (SELECT) {
+        // flag the row when any of its 32 columns pushed (OR over its 8 lanes)
+        int row_pushed = pushed;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) pushed += __shfl_xor(pushed, o, kWave);
-        if (lane == 0 && pushed) atomicAdd(&a.active[a.t], pushed);
+        for (int o = 1; o < kSlabVec; o <<= 1) row_pushed |= __shfl_xor(row_pushed, o, kWave);
+        if (owner && q == 0) a.flag_out[flag_off + v] = row_pushed ? 1 : 0;
+        __shared__ int block_pushed;
+        if (threadIdx.x == 0) block_pushed = 0;
+        __syncthreads();
+        if (pushed) block_pushed = 1;
+        __syncthreads();
+        if (threadIdx.x == 0 && block_pushed) a.active[a.t] = 1;
     }
 }
 
@@ -264,9 +321,9 @@ __global__ __launch_bounds__(256) void gfp_transpose_kernel(const float* __restr
     }
 }
 
-StreamGrid gfp_grid(int32_t n, int64_t ld) {
+StreamGrid gfp_grid(int32_t n, int32_t wide, int64_t ld) {
     StreamGrid g;
-    g.row_blocks = (n + kStreamRowsPerBlock - 1) / kStreamRowsPerBlock;
+    g.row_blocks = (wide + 3) / 4 + (n - wide + kStreamRowsPerBlock - 1) / kStreamRowsPerBlock;
     g.slabs = (int32_t)(ld / kSlab);
     g.full_rounds = ((int64_t)n * kSlab * 4 <= kStreamSlabBudget) ? g.slabs / kXcds : 0;
     return g;
@@ -322,26 +379,30 @@ ppr_status gfp_level_dppr(const ppr_csr* g, const int32_t* leaf_ptr, const int32
     const int32_t n = g->n;
     const int64_t ld = gfp_ld(k);
 
-    // Leaf lists first: nothing else is enqueued unless they are valid.
+    // Leaf lists first: no output is written unless they are valid.
     int32_t info[kGfpInfo] = {0, 0, 0, 0};
     fill<int32_t>(w.info, 0, kGfpInfo, s);
     hipLaunchKernelGGL(gfp_check_ptr_kernel, dim3((unsigned)((k + 256) / 256)), dim3(256), 0, s, leaf_ptr, k,
                        n_leaves, n, w.info);
     hipLaunchKernelGGL(gfp_check_idx_kernel, dim3((unsigned)std::min<int64_t>((n_leaves + 255) / 256, 4096)),
                        dim3(256), 0, s, leaf_idx, n_leaves, n, w.info);
+    // Row order by degree; the rows with more than kGfpWideDeg arcs come
+    // first, and their count is read back with the check results.
+    launch_degree(g->row_ptr, g->weight, n, w.deg, w.invd, s);
+    stream_row_order(g->row_ptr, n, w.hist, w.rows, s);
+    hipLaunchKernelGGL(gfp_wide_count_kernel, dim3(1), dim3(1), 0, s, w.hist, w.info);
     if ((st = launch_status()) != PPR_OK) return st;
     if ((st = read_i32(w.info, info, kGfpInfo, s)) != PPR_OK) return st;
     if (info[0] != 0) return PPR_EINVAL;
+    const int32_t wide = info[2];
 
-    launch_degree(g->row_ptr, g->weight, n, w.deg, w.invd, s);
-    stream_row_order(g->row_ptr, n, w.hist, w.rows, s);
     fill<float>(w.resid, 0.f, n * ld, s);
     fill<float>(w.est, 0.f, n * ld, s);
     fill<int32_t>(w.active, 0, max_rounds, s);
     hipLaunchKernelGGL(gfp_seed_kernel, dim3((unsigned)k), dim3(256), 0, s, leaf_ptr, leaf_idx, w.deg, n, w.resid);
 
     const bool weighted = g->weight != nullptr;
-    const StreamGrid grid = gfp_grid(n, ld);
+    const StreamGrid grid = gfp_grid(n, wide, ld);
     GfpRound a;
     a.rows = w.rows;
     a.col_idx = g->col_idx;
@@ -352,11 +413,15 @@ ppr_status gfp_level_dppr(const ppr_csr* g, const int32_t* leaf_ptr, const int32
     a.est = w.est;
     a.active = w.active;
     a.n = n;
+    a.wide = wide;
+    a.wide_blocks = (wide + 3) / 4;
     a.alpha = alpha;
     a.r_max = (float)r_max;
     a.t = 0;
     a.send_in = nullptr;
     a.send_out = w.send[0];
+    a.flag_in = nullptr;
+    a.flag_out = w.flag[0];
     gfp_launch_round<false, true>(weighted, a, grid, s);
 
     // Rounds 1 .. max_rounds - 1 in growing batches; after each batch the
@@ -371,6 +436,8 @@ ppr_status gfp_level_dppr(const ppr_csr* g, const int32_t* leaf_ptr, const int32
             a.t = t;
             a.send_in = w.send[(t - 1) & 1];
             a.send_out = w.send[t & 1];
+            a.flag_in = w.flag[(t - 1) & 1];
+            a.flag_out = w.flag[t & 1];
             gfp_launch_round<true, true>(weighted, a, grid, s);
         }
         launched = end;
@@ -392,6 +459,8 @@ ppr_status gfp_level_dppr(const ppr_csr* g, const int32_t* leaf_ptr, const int32
         a.t = 0;
         a.send_in = w.send[(rounds - 1) & 1];
         a.send_out = nullptr;
+        a.flag_in = w.flag[(rounds - 1) & 1];
+        a.flag_out = nullptr;
         gfp_launch_round<true, false>(weighted, a, grid, s);
     }
 

@@ -87,8 +87,10 @@ __device__ __forceinline__ void stream_block_map(const StreamGrid& g, int& slab,
 // classes (degrees from KEYS - 1 up share the first class), so that the 8
 // rows a streaming-step wave takes side by side have (nearly) equal arc
 // counts.  The order within a class is whatever the atomics give; it only
-// decides which rows share a wave, never a sum.  (The mid-size kernel reuses
-// the histogram and scan with exact classes and a stable scatter of its own.)
+// decides which rows share a wave, never a sum.  This histogram with one
+// global atomic per row serves the mid-size kernel's 65536 exact classes
+// (which do not fit in LDS; it has a stable scatter of its own); the
+// streaming row order below counts per block in LDS.
 template <int KEYS>
 static __global__ void stream_deg_hist_kernel(const int32_t* __restrict__ row_ptr, int32_t n,
                                               int32_t* __restrict__ hist) {
@@ -123,24 +125,65 @@ static __global__ __launch_bounds__(1024) void stream_deg_scan_kernel(int32_t* _
     }
 }
 
+// Streaming row order: the class counts are kept per block in LDS.  A block
+// counts its kOrderNodes rows there and adds each nonzero class count to the
+// global histogram once, then reserves one range per class with one atomic
+// and hands out positions inside it from LDS.  With a few hundred rows per
+// degree class in a block, this takes the global atomics on the few classes
+// of common degrees down from one per row to one per block and class.
+constexpr int kOrderNodes = 2048;
+
 template <int KEYS>
-static __global__ void stream_deg_scatter_kernel(const int32_t* __restrict__ row_ptr, int32_t n,
-                                                 int32_t* __restrict__ cursor, RowEnt* __restrict__ rows) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    const int rs = row_ptr[v], re = row_ptr[v + 1];
-    const int d = min(re - rs, KEYS - 1);
-    const int pos = atomicAdd(&cursor[KEYS - 1 - d], 1);
-    rows[pos] = RowEnt{rs, re, (int32_t)v, 0};
+static __global__ __launch_bounds__(1024) void stream_deg_hist_lds_kernel(const int32_t* __restrict__ row_ptr,
+                                                                          int32_t n, int32_t* __restrict__ hist) {
+    __shared__ int32_t cnt[KEYS];
+    for (int i = threadIdx.x; i < KEYS; i += blockDim.x) cnt[i] = 0;
+    __syncthreads();
+    const int64_t b = (int64_t)blockIdx.x * kOrderNodes;
+    const int64_t e = min((int64_t)n, b + kOrderNodes);
+    for (int64_t v = b + threadIdx.x; v < e; v += blockDim.x) {
+        const int d = min(row_ptr[v + 1] - row_ptr[v], KEYS - 1);
+        atomicAdd(&cnt[KEYS - 1 - d], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < KEYS; i += blockDim.x)
+        if (cnt[i]) atomicAdd(&hist[i], cnt[i]);
+}
+
+template <int KEYS>
+static __global__ __launch_bounds__(1024) void stream_deg_scatter_lds_kernel(const int32_t* __restrict__ row_ptr,
+                                                                             int32_t n, int32_t* __restrict__ cursor,
+                                                                             RowEnt* __restrict__ rows) {
+    __shared__ int32_t cnt[KEYS];
+    for (int i = threadIdx.x; i < KEYS; i += blockDim.x) cnt[i] = 0;
+    __syncthreads();
+    const int64_t b = (int64_t)blockIdx.x * kOrderNodes;
+    const int64_t e = min((int64_t)n, b + kOrderNodes);
+    for (int64_t v = b + threadIdx.x; v < e; v += blockDim.x) {
+        const int d = min(row_ptr[v + 1] - row_ptr[v], KEYS - 1);
+        atomicAdd(&cnt[KEYS - 1 - d], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < KEYS; i += blockDim.x)
+        if (cnt[i]) cnt[i] = atomicAdd(&cursor[i], cnt[i]);
+    __syncthreads();
+    for (int64_t v = b + threadIdx.x; v < e; v += blockDim.x) {
+        const int rs = row_ptr[v], re = row_ptr[v + 1];
+        const int d = min(re - rs, KEYS - 1);
+        const int pos = atomicAdd(&cnt[KEYS - 1 - d], 1);
+        rows[pos] = RowEnt{rs, re, (int32_t)v, 0};
+    }
 }
 
 template <int KEYS = kDegKeys>
 inline void stream_row_order(const int32_t* row_ptr, int32_t n, int32_t* hist, RowEnt* rows, hipStream_t s) {
+    static_assert(KEYS * 4 <= 32768, "per-block class counts must fit in LDS");
     fill<int32_t>(hist, 0, KEYS, s);
-    const unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(stream_deg_hist_kernel<KEYS>, dim3(blocks), dim3(256), 0, s, row_ptr, n, hist);
+    const unsigned blocks = (unsigned)((n + kOrderNodes - 1) / kOrderNodes);
+    hipLaunchKernelGGL(stream_deg_hist_lds_kernel<KEYS>, dim3(blocks), dim3(1024), 0, s, row_ptr, n, hist);
     hipLaunchKernelGGL(stream_deg_scan_kernel<KEYS>, dim3(1), dim3(1024), 0, s, hist);
-    hipLaunchKernelGGL(stream_deg_scatter_kernel<KEYS>, dim3(blocks), dim3(256), 0, s, row_ptr, n, hist, rows);
+    hipLaunchKernelGGL(stream_deg_scatter_lds_kernel<KEYS>, dim3(blocks), dim3(1024), 0, s, row_ptr, n, hist,
+                       rows);
 }
 
 __device__ __forceinline__ void f4_acc(float4& a, float4 y) {
@@ -170,19 +213,31 @@ __device__ __forceinline__ float4 slab_load(__amdgpu_buffer_rsrc_t r, uint32_t o
 // its row's neighbours in arc order, so a row's sum does not depend on which
 // rows share its wave.  Every lane of the wave must call it (dg = 0 for a
 // lane without a row).
-template <bool WEIGHTED>
+// FLAGGED: only neighbours u with flags[u] != 0 are read (the others count
+// as zero rows), and `got` is set when the row has such a neighbour.
+// STEP: arcs a lane group advances per pass; 8 when each group owns a row,
+// 64 when the wave's 8 groups share one row (group g then passes its row's
+// arcs from 8g on, and the caller adds the groups' sums).
+template <bool WEIGHTED, bool FLAGGED = false, int STEP = kSlabVec>
 __device__ __forceinline__ float4 slab_gather(__amdgpu_buffer_rsrc_t rin, const int32_t* __restrict__ col_idx,
                                               const float* __restrict__ weight, int rs, int dg, int lane,
-                                              uint32_t qoff) {
+                                              uint32_t qoff, const uint8_t* __restrict__ flags = nullptr,
+                                              int* got = nullptr) {
     const int q = lane % kSlabVec;
     int dmax = dg;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, kWave));
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    int any = 0;
     const int lead = (lane & ~(kSlabVec - 1)) * 4;  // ds_bpermute address of the group's first lane
-    for (int k0 = 0; k0 < dmax; k0 += kSlabVec) {
+    for (int k0 = 0; k0 < dmax; k0 += STEP) {
         const bool ok = k0 + q < dg;
-        const int idx = ok ? col_idx[rs + k0 + q] : -1;
+        int idx = ok ? col_idx[rs + k0 + q] : -1;
+        if (FLAGGED) {
+            const bool on = ok && flags[idx] != 0;
+            idx = on ? idx : -1;
+            any |= on ? 1 : 0;
+        }
         float wl = 0.f;
         if (WEIGHTED) wl = ok ? weight[rs + k0 + q] : 0.f;
         float4 y[kSlabVec];
@@ -200,6 +255,12 @@ __device__ __forceinline__ float4 slab_gather(__amdgpu_buffer_rsrc_t rin, const 
                 f4_acc(acc, y[j]);
             }
         }
+    }
+    if (FLAGGED) {
+        // OR over the 8 lanes of the row
+#pragma unroll
+        for (int o = 1; o < kSlabVec; o <<= 1) any |= __shfl_xor(any, o, kWave);
+        *got = any;
     }
     return acc;
 }

@@ -108,6 +108,45 @@ def test_threshold_result_is_valid(ops, weighted, r_max):
     assert np.all(np.abs(got - e_o) <= bound[None, :] + tol)
 
 
+@pytest.mark.parametrize("weighted", [False, True])
+def test_rows_gathered_by_a_whole_wave(ops, weighted):
+    # Chung-Lu n = 4000, exponent 2.0, mean degree 60: 180 rows have more
+    # than 256 arcs (up to 456) and take the whole-wave gather; ragged
+    # supernodes over a random part of V.
+    g0 = synth.chung_lu(4000, 2.0, 60, synth.BASE_SEED + 41)
+    w = None
+    if weighted:
+        w = np.random.default_rng(synth.BASE_SEED + 42).uniform(0.5, 2.0, g0.m_und).astype(np.float32)
+    g = synth.build_graph(g0.n, g0.eu, g0.ev, w)
+    assert (np.diff(g.row_ptr) > 256).sum() > 100
+    leaves = _ragged(g.n, 12, synth.BASE_SEED + 43)
+    W = O.weight_matrix(g.n, g.eu, g.ev, g.weight)
+    d = O.degrees(W)
+    csr = ops.Csr.from_graph(g, "cuda")
+    P = O.transition(W)
+    for T in (1, 7, 30):
+        print(f"[gfp wide zero] weighted={weighted} T={T}", flush=True)
+        out, est, _, rounds, _ = ops.gfp_level_dppr(csr, leaves, ALPHA, 0.0, T, want_est=True, allow_noconv=True)
+        ppr, _, _ = O.ppr_power_iteration(P, np.arange(g.n), ALPHA, fixed_iters=T)
+        want = O.level_dppr(ppr * d[:, None], leaves)
+        assert np.abs(out.double().cpu().numpy() - want).max() <= REL * np.abs(want).max()
+        _, _, ne_o, _, _ = O.group_forward_push_rounds(W, leaves, ALPHA, 0.0, T)
+        assert np.abs(est.double().cpu().numpy() - ne_o).max() <= REL * np.abs(ne_o).max()
+    r_max = 1e-6
+    print(f"[gfp wide valid] weighted={weighted}", flush=True)
+    out, _, resid, _, _ = ops.gfp_level_dppr(csr, leaves, ALPHA, r_max, 10000, want_resid=True)
+    pi_d = O.ppr_closed_form(P, ALPHA) * d[:, None]
+    L = O.level_dppr(pi_d, leaves)
+    R = resid.double().cpu().numpy()
+    got = out.double().cpu().numpy()
+    assert np.all(R <= d[None, :] * r_max * (1 + 1e-5))
+    err = O.gfp_error_term(pi_d, leaves, R, d)
+    assert np.abs(got + err - L).max() <= REL * np.abs(L).max()
+    bound = r_max * np.array([d[F].mean() for F in leaves])
+    tol = REL * np.abs(L).max()
+    assert np.all(L - got >= -tol) and np.all(L - got <= bound[None, :] + tol)
+
+
 def test_round_cap_keeps_the_invariant(ops):
     g, leaves = _case(700, 4, False, synth.BASE_SEED + 23)
     W, pi_d, d = _exact(g)
