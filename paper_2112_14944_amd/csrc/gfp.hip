@@ -118,14 +118,14 @@ __global__ void gfp_wide_count_kernel(const int32_t* __restrict__ hist, int32_t*
 
 // Initial residues: d(v) / |F(V_i)| in column i at each leaf v of V_i.  A
 // leaf listed twice in one set receives its share twice.
+// Blocks (i, *) take the leaves of set i, 256 at a time.
 __global__ void gfp_seed_kernel(const int32_t* __restrict__ leaf_ptr, const int32_t* __restrict__ leaf_idx,
                                 const float* __restrict__ deg, int32_t n, float* __restrict__ resid) {
     const int i = blockIdx.x;
     const int b = leaf_ptr[i], e = leaf_ptr[i + 1];
-    const float size = (float)(e - b);
-    for (int p = b + threadIdx.x; p < e; p += blockDim.x) {
+    for (int p = b + (int)blockIdx.y * 256 + (int)threadIdx.x; p < e; p += (int)gridDim.y * 256) {
         const int32_t v = leaf_idx[p];
-        atomicAdd(&resid[sidx(v, i, n)], deg[v] / size);
+        atomicAdd(&resid[sidx(v, i, n)], deg[v] / (float)(e - b));
     }
 }
 
@@ -274,8 +274,19 @@ __global__ __launch_bounds__(256) void gfp_aggregate_kernel(const float* __restr
     const int64_t e = min((int64_t)leaf_ptr[j + 1], b + kGfpChunk);
     for (int64_t slab = 0; slab < ld / kSlab; ++slab) {
         const float* x = est + slab * n * kSlab;
+        // four leaves in flight per lane, added in leaf order
         double s = 0.0;
-        for (int64_t p = b + g; p < e; p += 8) s += (double)x[(int64_t)leaf_idx[p] * kSlab + c];
+        int64_t p = b + g;
+        for (; p + 24 < e; p += 32) {
+            const int32_t v0 = leaf_idx[p], v1 = leaf_idx[p + 8], v2 = leaf_idx[p + 16], v3 = leaf_idx[p + 24];
+            const float x0 = x[(int64_t)v0 * kSlab + c], x1 = x[(int64_t)v1 * kSlab + c];
+            const float x2 = x[(int64_t)v2 * kSlab + c], x3 = x[(int64_t)v3 * kSlab + c];
+            s += (double)x0;
+            s += (double)x1;
+            s += (double)x2;
+            s += (double)x3;
+        }
+        for (; p < e; p += 8) s += (double)x[(int64_t)leaf_idx[p] * kSlab + c];
         red[g][c] = s;
         __syncthreads();
         if (g == 0) {
@@ -399,7 +410,9 @@ ppr_status gfp_level_dppr(const ppr_csr* g, const int32_t* leaf_ptr, const int32
     fill<float>(w.resid, 0.f, n * ld, s);
     fill<float>(w.est, 0.f, n * ld, s);
     fill<int32_t>(w.active, 0, max_rounds, s);
-    hipLaunchKernelGGL(gfp_seed_kernel, dim3((unsigned)k), dim3(256), 0, s, leaf_ptr, leaf_idx, w.deg, n, w.resid);
+    hipLaunchKernelGGL(gfp_seed_kernel, dim3((unsigned)k, (unsigned)std::min(4096, (info[1] + 255) / 256)),
+                       dim3(256), 0, s,
+                       leaf_ptr, leaf_idx, w.deg, n, w.resid);
 
     const bool weighted = g->weight != nullptr;
     const StreamGrid grid = gfp_grid(n, wide, ld);

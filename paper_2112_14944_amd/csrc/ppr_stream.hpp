@@ -230,16 +230,23 @@ __device__ __forceinline__ float4 slab_gather(__amdgpu_buffer_rsrc_t rin, const 
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     int any = 0;
     const int lead = (lane & ~(kSlabVec - 1)) * 4;  // ds_bpermute address of the group's first lane
+    // the arc indices (and weights) of the next pass are loaded one pass
+    // ahead, so that a long row's passes wait on one load each, not two
+    int idx_next = q < dg ? col_idx[rs + q] : -1;
+    float wl_next = 0.f;
+    if (WEIGHTED) wl_next = q < dg ? weight[rs + q] : 0.f;
     for (int k0 = 0; k0 < dmax; k0 += STEP) {
         const bool ok = k0 + q < dg;
-        int idx = ok ? col_idx[rs + k0 + q] : -1;
+        int idx = idx_next;
+        const float wl = wl_next;
+        const bool ok_next = k0 + STEP + q < dg;
+        idx_next = ok_next ? col_idx[rs + k0 + STEP + q] : -1;
+        if (WEIGHTED) wl_next = ok_next ? weight[rs + k0 + STEP + q] : 0.f;
         if (FLAGGED) {
             const bool on = ok && flags[idx] != 0;
             idx = on ? idx : -1;
             any |= on ? 1 : 0;
         }
-        float wl = 0.f;
-        if (WEIGHTED) wl = ok ? weight[rs + k0 + q] : 0.f;
         float4 y[kSlabVec];
 #pragma unroll
         for (int j = 0; j < kSlabVec; ++j) {
