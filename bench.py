@@ -203,7 +203,35 @@ def spmm_large(ops, dev, n=1_000_000, gamma=2.2, avg_degree=30, n_src=4096, tol=
                 nnz=nnz), (g, csr)
 
 
-def gfp_level(ops, dev, g, csr, k=25, reps=3):
+def gfp_cpu_oracle(g, k, r_max, sample=4):
+    """The FP64 oracle's rounds (oracle.group_forward_push_rounds, unchanged)
+    on the same graph and threshold for `sample` of the k source supernodes
+    (evenly spaced), timed on the host and scaled by k / sample: the source
+    columns are independent, so the work is linear in their number."""
+    import oracle as O
+    import synth
+
+    W = O.weight_matrix(g.n, g.eu, g.ev)
+    leaves = []
+    start = 0
+    for sz in synth.equal_blocks(g.n, k):
+        leaves.append(np.arange(start, start + sz))
+        start += sz
+    pick = [leaves[i] for i in np.linspace(0, k - 1, sample).round().astype(int)]
+    t0 = time.perf_counter()
+    _, _, _, rounds, _ = O.group_forward_push_rounds(W, pick, ALPHA, r_max, 10000)
+    dt = (time.perf_counter() - t0) * k / sample
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    return dict(ms=dt * 1e3, rounds=rounds, cores=int(threads), kind="oracle",
+                sample=f"{sample} of the {k} source supernodes (and the same {sample} as targets), every round, "
+                       f"{dt * sample / k:.1f} s, extrapolated linearly to {k}")
+
+
+def gfp_level(ops, dev, g, csr, k=25, reps=3, cpu=False):
     """Level-l DPPR among the k = 25 children of the top supernode of the
     10^6-node Chung-Lu graph above, by Group Forward-Push in rounds (one
     gfp_level_dppr call from all 25 source supernodes).  The children
@@ -238,11 +266,13 @@ def gfp_level(ops, dev, g, csr, k=25, reps=3):
         best = t if best is None else min(best, t)
     ld = 32 * ((k + 31) // 32)
     alg = rounds * (16.0 * n * ld + 4.0 * nnz + 24.0 * n)
+    cpu_o = gfp_cpu_oracle(g, k, r_max) if cpu else None
     return dict(workload=f"chung_lu n={n} gamma=2.2 mean degree 30, k={k} supernodes partitioning V, "
                          f"r_max={r_max:.3e} (eps 1-1/e, delta 1/(10k), tau 1/sqrt(kn)), whole gfp_level_dppr call",
                 kernel="gfp_round_kernel", ms=best, rounds=rounds, bound="hbm", unit="GB/s",
                 achieved=alg / (best * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
-                frac=alg / (best * 1e-3) / 1e9 / PEAK_HBM_GBS, work=f"{alg:.4g} B over {rounds} rounds")
+                frac=alg / (best * 1e-3) / 1e9 / PEAK_HBM_GBS, work=f"{alg:.4g} B over {rounds} rounds",
+                cpu_oracle=cpu_o)
 
 
 def counters_pass(ops, b, x0, dev):
@@ -299,7 +329,7 @@ def main():
     dev = "cuda:0"
     if args.only_gfp:
         g_big = synth.chung_lu(1_000_000, 2.2, 30, synth.BASE_SEED + 4)
-        gfp = gfp_level(ops, dev, g_big, ops.Csr.from_graph(g_big, dev))
+        gfp = gfp_level(ops, dev, g_big, ops.Csr.from_graph(g_big, dev), cpu=not args.no_cpu_baseline)
         log(f"level-l DPPR by group forward push (n = 10^6, k = 25): {gfp['ms']:.2f} ms, "
             f"{gfp['rounds']} rounds, {gfp['achieved']:.0f} GB/s algorithmic")
         print(json.dumps({"level_dppr_gfp": gfp}), flush=True)
@@ -435,7 +465,7 @@ def main():
         log(f"4096-source SpMM (n = 10^6): {spmm_big['ms']:.1f} ms, {spmm_big['achieved']:.0f} GB/s algorithmic")
         if not args.no_gfp:
             torch.cuda.empty_cache()
-            gfp = gfp_level(ops, dev, g_big, csr_big)
+            gfp = gfp_level(ops, dev, g_big, csr_big, cpu=not args.no_cpu_baseline)
             log(f"level-l DPPR by group forward push (n = 10^6, k = 25): {gfp['ms']:.2f} ms, "
                 f"{gfp['rounds']} rounds, {gfp['achieved']:.0f} GB/s algorithmic")
         del g_big, csr_big
