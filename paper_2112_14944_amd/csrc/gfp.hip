@@ -230,7 +230,13 @@ __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid g
                 add[c] = on ? a.alpha * r[c] : 0.f;
                 r[c] = on ? 0.f : r[c];
             }
-            *reinterpret_cast<float4*>(a.send_out + off) = make_float4(s[0], s[1], s[2], s[3]);
+            // what a row sends is read only when the row is flagged, i.e.
+            // when one of its 8 lanes pushed: the others write their zeros
+            // only then
+            int row_any = pushed;
+#pragma unroll
+            for (int o = 1; o < kSlabVec; o <<= 1) row_any |= __shfl_xor(row_any, o, kWave);
+            if (row_any) *reinterpret_cast<float4*>(a.send_out + off) = make_float4(s[0], s[1], s[2], s[3]);
             if (pushed) {
                 float4* e4 = reinterpret_cast<float4*>(a.est + off);
                 float4 ev = *e4;

@@ -230,23 +230,28 @@ __device__ __forceinline__ float4 slab_gather(__amdgpu_buffer_rsrc_t rin, const 
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     int any = 0;
     const int lead = (lane & ~(kSlabVec - 1)) * 4;  // ds_bpermute address of the group's first lane
-    // the arc indices (and weights) of the next pass are loaded one pass
-    // ahead, so that a long row's passes wait on one load each, not two
-    int idx_next = q < dg ? col_idx[rs + q] : -1;
-    float wl_next = 0.f;
-    if (WEIGHTED) wl_next = q < dg ? weight[rs + q] : 0.f;
+    // Software pipeline over the passes: arc indices are loaded two passes
+    // ahead, weights and push flags one pass ahead, so that a long row's
+    // pass waits only on its own gathers.
+    int idx_cur = q < dg ? col_idx[rs + q] : -1;
+    int idx_next = STEP + q < dg ? col_idx[rs + STEP + q] : -1;
+    float wl_cur = 0.f;
+    if (WEIGHTED) wl_cur = q < dg ? weight[rs + q] : 0.f;
+    bool on_cur = true;
+    if (FLAGGED) on_cur = idx_cur >= 0 && flags[idx_cur] != 0;
     for (int k0 = 0; k0 < dmax; k0 += STEP) {
-        const bool ok = k0 + q < dg;
-        int idx = idx_next;
-        const float wl = wl_next;
-        const bool ok_next = k0 + STEP + q < dg;
-        idx_next = ok_next ? col_idx[rs + k0 + STEP + q] : -1;
-        if (WEIGHTED) wl_next = ok_next ? weight[rs + k0 + STEP + q] : 0.f;
+        int idx = idx_cur;
+        const float wl = wl_cur;
+        const bool on = on_cur;
+        const int idx_after = k0 + 2 * STEP + q < dg ? col_idx[rs + k0 + 2 * STEP + q] : -1;
+        if (WEIGHTED) wl_cur = k0 + STEP + q < dg ? weight[rs + k0 + STEP + q] : 0.f;
         if (FLAGGED) {
-            const bool on = ok && flags[idx] != 0;
+            on_cur = idx_next >= 0 && flags[idx_next] != 0;
             idx = on ? idx : -1;
             any |= on ? 1 : 0;
         }
+        idx_cur = idx_next;
+        idx_next = idx_after;
         float4 y[kSlabVec];
 #pragma unroll
         for (int j = 0; j < kSlabVec; ++j) {
