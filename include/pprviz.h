@@ -224,6 +224,34 @@ ppr_status stress_eval(const float* delta, int32_t k, const float* x, double* st
 ppr_status layout_step(const float* delta, int32_t k, const float* x_in, float* x_out,
                        double* stress_out, void* ws, size_t ws_bytes, void* stream);
 
+/* Workspace bytes needed by layout_step_exact. */
+size_t layout_exact_workspace(int32_t k);
+
+/*
+ * The exact stress-majorization step (the appendix's Guttman transform,
+ * eq:pprlayout-leq): x_out = (L^w)^+ L^Y(x_in) x_in, with
+ *   L^w_ij = -Delta_ij^-2 and L^Y_ij = -1 / (Delta_ij ||Y_i - Y_j||) for i != j
+ *   (0 for a coincident pair), each diagonal the negated row sum.
+ * L^w is singular (its rows sum to zero), so the solution taken is the one
+ * with zero centroid, the pseudo-inverse's.  It is reached by conjugate
+ * gradients on the x and y coordinates side by side, started from the
+ * centred x_in, each applying L^w by one pass over Delta (4 k^2 bytes), until
+ * ||L^w x - L^Y(x_in) x_in|| <= cg_tol * ||L^Y(x_in) x_in|| for both
+ * coordinates or after cg_max_iter iterations (then PPR_ENOCONV, x_out holds
+ * the last iterate).  The step never increases the stress of a converged
+ * solve (majorization).  Dot products are summed in FP64 in a fixed order;
+ * everything else is FP32.
+ *  delta     float[k*k], symmetric, positive off the diagonal (read only off it)
+ *  x_in      float[k*2]; x_out float[k*2], != x_in
+ *  cg_iters_out HOST int32 or NULL: iterations run.
+ * The call synchronizes `stream` every few iterations to read the stop flag.
+ * Returns PPR_EINVAL for NULL arrays, k < 1, x_in == x_out, cg_tol < 0 or not
+ * finite, cg_max_iter < 0.
+ */
+ppr_status layout_step_exact(const float* delta, int32_t k, const float* x_in, float* x_out,
+                             double cg_tol, int32_t cg_max_iter, int32_t* cg_iters_out,
+                             void* ws, size_t ws_bytes, void* stream);
+
 /*
  * Gradient of grad_scale * L(X | Delta) (Eq. eq:loss):
  *   grad_x[i]  = grad_scale * sum_{j!=i} 2 w_ij (d_ij - Delta_ij)(X_i - X_j)/d_ij

@@ -183,6 +183,21 @@ def layout(delta, x0, steps):
     return a
 
 
+def layout_step_exact(delta, x, cg_tol=1e-6, cg_max_iter=1000, out=None, allow_noconv=False):
+    """The exact (Guttman) stress-majorization step by conjugate gradients.
+    Returns (x_out [k, 2], CG iterations)."""
+    _check_layout(delta, x)
+    k = delta.shape[0]
+    out = torch.empty_like(x) if out is None else out
+    ws = _ws(L.lib().layout_exact_workspace(k), delta.device)
+    iters = C.c_int32()
+    st = L.lib().layout_step_exact(_ptr(delta), k, _ptr(x), _ptr(out), cg_tol, cg_max_iter, C.byref(iters),
+                                   _ptr(ws), ws.numel(), _stream(delta.device))
+    allow = (L.PPR_OK, L.PPR_ENOCONV) if allow_noconv else (L.PPR_OK,)
+    L.check("layout_step_exact", st, allow)
+    return out, iters.value
+
+
 def stress_backward(delta, x, grad_scale=1.0, want_grad_x=True, want_grad_delta=True):
     k = _check_layout(delta, x)
     gx = torch.empty_like(x) if want_grad_x else None
