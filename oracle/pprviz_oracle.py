@@ -432,3 +432,40 @@ def grad_x_rows(X, D_rows, rows):
         coef[pos] = 2.0 * (dist[pos] - Di[mask][pos]) / (Di[mask][pos] ** 2 * dist[pos])
         out[k] = (coef[:, None] * diff).sum(0)
     return out
+
+
+# --------------------------------------------------------------------------
+# Aesthetic metrics of a layout (Section 2.1, Definitions def:node-distri and
+# def:edge-var)
+# --------------------------------------------------------------------------
+
+
+def node_distribution(X):
+    """ND(X) = sum_{i<j} 1 / ||X_i - X_j||^2 (Definition def:node-distri), by
+    a plain double loop; a coincident pair makes it infinite."""
+    X = np.asarray(X, dtype=np.float64)
+    k = X.shape[0]
+    total = 0.0
+    for i in range(k):
+        for j in range(i + 1, k):
+            d2 = (X[i, 0] - X[j, 0]) ** 2 + (X[i, 1] - X[j, 1]) ** 2
+            total += math.inf if d2 == 0.0 else 1.0 / d2
+    return total
+
+
+def ulcv(X, eu, ev):
+    """ULCV(X) = l_sigma / l_mu over the edge lengths ||X_u - X_v|| of the
+    listed edges (Definition def:edge-var), with the population standard
+    deviation (the paper does not say which; this reading divides by the
+    edge count).  NaN when there is no edge or every edge has length 0."""
+    X = np.asarray(X, dtype=np.float64)
+    eu = np.asarray(eu, dtype=np.int64)
+    ev = np.asarray(ev, dtype=np.int64)
+    if eu.size == 0:
+        return math.nan
+    lengths = [math.hypot(X[u, 0] - X[v, 0], X[u, 1] - X[v, 1]) for u, v in zip(eu, ev)]
+    mu = sum(lengths) / len(lengths)
+    if mu == 0.0:
+        return math.nan
+    var = sum((l - mu) ** 2 for l in lengths) / len(lengths)
+    return math.sqrt(var) / mu
