@@ -201,7 +201,32 @@ def spmm_large(ops, dev, n=1_000_000, gamma=2.2, avg_degree=30, n_src=4096, tol=
                 kernel="stream_step_kernel", ms=best, bound="hbm", unit="GB/s",
                 achieved=alg / (best * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
                 frac=alg / (best * 1e-3) / 1e9 / PEAK_HBM_GBS, work=f"{alg:.4g} B over {T - 1} pushes",
-                nnz=nnz), (g, csr, delta)
+                nnz=nnz), (g, csr, delta, src)
+
+
+def layout_metrics_leg(ops, dev, x, g, src, reps=3):
+    """ND and ULCV (Section 2.1) of the 4096-node layout: ND over all pairs,
+    ULCV over the edges of the graph induced on the 4096 sources.  Timed
+    whole calls (each synchronizes to return its two numbers)."""
+    import torch
+    import synth
+
+    pos = np.full(g.n, -1, dtype=np.int64)
+    pos[np.asarray(src)] = np.arange(len(src))
+    keep = (pos[g.eu] >= 0) & (pos[g.ev] >= 0)
+    sub = synth.build_graph(len(src), pos[g.eu[keep]], pos[g.ev[keep]])
+    csr = ops.Csr.from_graph(sub, dev)
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nd, ul = ops.layout_metrics(x, csr)
+        t = (time.perf_counter() - t0) * 1e3
+        best = t if best is None else min(best, t)
+    k = x.shape[0]
+    return dict(workload=f"ND over the {k * (k - 1) // 2} pairs of the 4096-node layout after the exact step; "
+                         f"ULCV over the {sub.m_und} edges induced on its nodes", nd=nd, ulcv=ul, ms=best,
+                kernel="nd_kernel", pairs=k * (k - 1) // 2)
 
 
 def layout_exact_leg(ops, dev, delta, sweeps=200, reps=3, cpu=False):
@@ -242,7 +267,8 @@ def layout_exact_leg(ops, dev, delta, sweeps=200, reps=3, cpu=False):
         dt = time.perf_counter() - t0
         cpu_o = dict(ms=dt * 8e3, kind="oracle", sample=f"one step at k={kc} (the leading block of Delta), "
                      f"{dt:.1f} s, scaled by (k/{kc})^3 = 8 for the pseudo-inverse")
-    return dict(workload=f"exact stress-majorization step, k={k} (PDist among the 4096 sources of the "
+    exact_x = x
+    return exact_x, dict(workload=f"exact stress-majorization step, k={k} (PDist among the 4096 sources of the "
                          f"10^6-node graph), from the layout after {sweeps} Jacobi sweeps, CG to 1e-6",
                 kernel="cg_rows_kernel", ms=best, cg_iters=iters, stress_before=s_y, stress_after=s_x,
                 bound="hbm", unit="GB/s", achieved=alg / (best * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
@@ -504,16 +530,19 @@ def main():
     spmm_big = None
     gfp = None
     exact = None
+    metrics = None
     if not args.no_spmm_large:
         del bufs
         plan.close()
         plan = None
         torch.cuda.empty_cache()
-        spmm_big, (g_big, csr_big, delta_big) = spmm_large(ops, dev)
+        spmm_big, (g_big, csr_big, delta_big, src_big) = spmm_large(ops, dev)
         log(f"4096-source SpMM (n = 10^6): {spmm_big['ms']:.1f} ms, {spmm_big['achieved']:.0f} GB/s algorithmic")
-        exact = layout_exact_leg(ops, dev, delta_big, cpu=not args.no_cpu_baseline)
+        x_exact, exact = layout_exact_leg(ops, dev, delta_big, cpu=not args.no_cpu_baseline)
         log(f"exact majorization step (k = 4096): {exact['ms']:.2f} ms, {exact['cg_iters']} CG iterations, "
             f"{exact['achieved']:.0f} GB/s algorithmic; stress {exact['stress_before']:.10g} -> {exact['stress_after']:.10g}")
+        metrics = layout_metrics_leg(ops, dev, x_exact, g_big, src_big)
+        log(f"layout metrics (k = 4096): ND {metrics['nd']:.6g}, ULCV {metrics['ulcv']:.4f}, {metrics['ms']:.2f} ms")
         del delta_big
         if not args.no_gfp:
             torch.cuda.empty_cache()
@@ -554,6 +583,7 @@ def main():
         "spmm_large": spmm_big,
         "level_dppr_gfp": gfp,
         "layout_exact": exact,
+        "layout_metrics": metrics,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

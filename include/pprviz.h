@@ -252,6 +252,23 @@ ppr_status layout_step_exact(const float* delta, int32_t k, const float* x_in, f
                              double cg_tol, int32_t cg_max_iter, int32_t* cg_iters_out,
                              void* ws, size_t ws_bytes, void* stream);
 
+/* Workspace bytes needed by layout_metrics. */
+size_t layout_metrics_workspace(int32_t k);
+
+/*
+ * Aesthetic metrics of a layout (Section 2.1):
+ *  nd_out   HOST double or NULL: ND(X) = sum_{i<j} 1 / ||X_i - X_j||^2
+ *           (Definition def:node-distri); +inf when two points coincide.
+ *  ulcv_out HOST double or NULL: ULCV(X) = l_sigma / l_mu over the edge lengths
+ *           of g (Definition def:edge-var), the population standard deviation;
+ *           NaN when g has no arc or every edge has length 0.  g->n must be k.
+ * x is float[k*2].  Sums are FP64 in a fixed order.  The call synchronizes
+ * `stream`.  Returns PPR_EINVAL for NULL x, k < 1, both outputs NULL, or a
+ * missing / mismatched g when ulcv_out is asked for.
+ */
+ppr_status layout_metrics(const float* x, int32_t k, const ppr_csr* g, double* nd_out,
+                          double* ulcv_out, void* ws, size_t ws_bytes, void* stream);
+
 /*
  * Gradient of grad_scale * L(X | Delta) (Eq. eq:loss):
  *   grad_x[i]  = grad_scale * sum_{j!=i} 2 w_ij (d_ij - Delta_ij)(X_i - X_j)/d_ij

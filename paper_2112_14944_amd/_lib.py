@@ -51,6 +51,8 @@ _SIGS = {
     "stress_eval": (C.c_int, [vp, i32, vp, vp, vp, sz, vp]),
     "layout_step": (C.c_int, [vp, i32, vp, vp, vp, vp, sz, vp]),
     "stress_backward": (C.c_int, [vp, i32, vp, f32, vp, vp, vp]),
+    "layout_metrics_workspace": (sz, [i32]),
+    "layout_metrics": (C.c_int, [vp, i32, C.POINTER(ppr_csr), C.POINTER(f64), C.POINTER(f64), vp, sz, vp]),
     "layout_exact_workspace": (sz, [i32]),
     "layout_step_exact": (C.c_int, [vp, i32, vp, vp, f64, i32, C.POINTER(i32), vp, sz, vp]),
     "ppr_backward_workspace": (sz, [C.POINTER(ppr_csr), C.c_int]),

@@ -183,6 +183,21 @@ def layout(delta, x0, steps):
     return a
 
 
+def layout_metrics(x, g: Csr | None = None):
+    """(ND, ULCV) of a layout; ULCV is None without a graph."""
+    _require_cuda(x)
+    k = x.shape[0]
+    assert x.shape == (k, 2) and x.dtype == torch.float32 and x.is_contiguous()
+    ws = _ws(L.lib().layout_metrics_workspace(k), x.device)
+    nd = C.c_double()
+    ul = C.c_double()
+    cg = g.c() if g is not None else None
+    st = L.lib().layout_metrics(_ptr(x), k, C.byref(cg) if cg is not None else None, C.byref(nd),
+                                C.byref(ul) if g is not None else None, _ptr(ws), ws.numel(), _stream(x.device))
+    L.check("layout_metrics", st)
+    return nd.value, (ul.value if g is not None else None)
+
+
 def layout_step_exact(delta, x, cg_tol=1e-6, cg_max_iter=1000, out=None, allow_noconv=False):
     """The exact (Guttman) stress-majorization step by conjugate gradients.
     Returns (x_out [k, 2], CG iterations)."""
