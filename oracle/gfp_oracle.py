@@ -15,12 +15,19 @@ leaf sets of the k supernodes of S need not cover V (residue flows through
 nodes outside S) and may in principle overlap; every formula below is the
 paper's with F(V_i) read as the given list.
 
+It also holds the Group Backward-Push (Algorithm alg:bwdpushsn), the DNPR of
+Eq. eq:dnpr-dnppr, the backward threshold of Eq. eq:brmax and Tau-Push
+(Algorithm alg:taupush).
+
 Pins (tests/test_oracle_gfp.py): the complete-graph closed form, symmetry and
-column sums of the level-l DPPR of an undirected graph, the printed first push
-of Section 3.3's running example, the invariant against the exact inverse at
-every stopping point, the termination rule, the error bound of Lemma
-lem:fpsn-correct, and the power-iteration series that the rounds reduce to
-when the threshold is zero.  No function here is "parity unpinned".
+column sums of the level-l DPPR of an undirected graph, the printed first
+pushes of Section 3.3's forward example and Section 4.1's backward example,
+the forward and backward invariants against the exact inverse at every
+stopping point (also on a directed graph), the termination rules, the error
+bounds of Lemmas lem:fpsn-correct and lem:bpsn-correct, the power-iteration
+series that the rounds of both directions reduce to when the threshold is
+zero, the DNPR of an undirected graph against its definition, and Tau-Push's
+eps * delta bound.  No function here is "parity unpinned".
 """
 from __future__ import annotations
 
@@ -191,3 +198,166 @@ def gfp_error_term(pi_d, leaves, R, d):
         Fj = np.asarray(Fj, dtype=np.int64)
         out[:, j] = (Rs @ pi_d[:, Fj]).sum(axis=1) / Fj.size
     return out
+
+
+# --------------------------------------------------------------------------
+# Group Backward-Push (Algorithm alg:bwdpushsn), DNPR (Eq. eq:dnpr-dnppr) and
+# Tau-Push (Algorithm alg:taupush)
+# --------------------------------------------------------------------------
+
+
+def group_backward_push(W, leaves, j, alpha, rb_max, max_pushes=None):
+    """Algorithm alg:bwdpushsn towards target supernode V_j, one push at a time.
+
+    Residues r(v) start at 1 / |F(V_j)| on the leaves of V_j.  While some node
+    v_k holds more than rb_max: r(v_k) is set to 0; if v_k is a leaf of a
+    supernode V_i of S, alpha d(v_k) r / |F(V_i)| is added to the estimate
+    pi_d(V_i, V_j); each in-neighbour v_i of v_k receives (1 - alpha) r
+    w_ik / d(v_i) (the walk's step probability from v_i to v_k; 1 / d(v_i)
+    with unit weights).  FIFO order, as in group_forward_push.
+
+    Returns (estimate over the k source supernodes, residue over the n nodes,
+    number of pushes)."""
+    W = sp.csr_matrix(W)
+    d = degrees(W)
+    Wt = sp.csr_matrix(W.T)  # row v_k lists the in-neighbours v_i and w_ik
+    indptr, indices, data = Wt.indptr, Wt.indices, Wt.data
+    n = d.shape[0]
+    k = len(leaves)
+    member = [[] for _ in range(n)]
+    for i, Fi in enumerate(leaves):
+        for v in np.asarray(Fi, dtype=np.int64):
+            member[int(v)].append(i)
+    size = [len(Fi) for Fi in leaves]
+    r = np.zeros(n)
+    Fj = np.asarray(leaves[j], dtype=np.int64)
+    np.add.at(r, Fj, 1.0 / Fj.size)
+    est = np.zeros(k)
+    queue = collections.deque(v for v in range(n) if r[v] > rb_max)
+    queued = np.zeros(n, dtype=bool)
+    queued[list(queue)] = True
+    pushes = 0
+    while queue:
+        if max_pushes is not None and pushes >= max_pushes:
+            break
+        v = queue.popleft()
+        queued[v] = False
+        if not r[v] > rb_max:
+            continue
+        rv = r[v]
+        r[v] = 0.0
+        for i in member[v]:
+            est[i] += alpha * d[v] * rv / size[i]
+        for e in range(indptr[v], indptr[v + 1]):
+            u = indices[e]
+            r[u] += (1.0 - alpha) * rv * data[e] / d[u]
+            if not queued[u] and r[u] > rb_max:
+                queue.append(u)
+                queued[u] = True
+        pushes += 1
+    return est, r, pushes
+
+
+def group_backward_push_rounds(W, leaves, targets, alpha, rb_max, max_rounds):
+    """The backward pushes towards every target supernode in `targets` at
+    once, in synchronous rounds (as group_forward_push_rounds): each round
+    every (node, target) pair whose residue exceeds its target's threshold
+    rb_max[j] (a scalar or one value per target) pushes it, and what arrives
+    waits for the next round.  Pushing part of a residue keeps the backward
+    invariant, so the result satisfies it, the stopping rule and the error
+    bound of Lemma lem:bpsn-correct.  With rb_max = 0, T rounds give the
+    power series truncated at T terms.
+
+    Returns (estimate k x len(targets) [i, c] for target targets[c],
+    residue len(targets) x n, per-node estimate alpha d(v) sum r, rounds,
+    pairs pushed in the last round)."""
+    W = sp.csr_matrix(W)
+    d = degrees(W)
+    n = d.shape[0]
+    k = len(leaves)
+    t = len(targets)
+    inv = np.zeros(n)
+    nz = d > 0
+    inv[nz] = 1.0 / d[nz]
+    R = np.zeros((t, n))
+    for c, j in enumerate(targets):
+        Fj = np.asarray(leaves[j], dtype=np.int64)
+        np.add.at(R[c], Fj, 1.0 / Fj.size)
+    th = np.broadcast_to(np.asarray(rb_max, dtype=np.float64), (t,))[:, None]
+    node_est = np.zeros((t, n))
+    sent = np.zeros((t, n))
+    rounds = 0
+    active = 0
+    while rounds < max_rounds:
+        if rounds > 0:
+            # node v_i receives (1 - alpha) sum_k w_ik r(v_k) / d(v_i)
+            R = R + (1.0 - alpha) * np.asarray(W @ sent.T).T * inv[None, :]
+        mask = R > th
+        active = int(mask.sum())
+        node_est += alpha * d[None, :] * np.where(mask, R, 0.0)
+        sent = np.where(mask, R, 0.0)
+        R = np.where(mask, 0.0, R)
+        rounds += 1
+        if active == 0:
+            break
+    if active:
+        R = R + (1.0 - alpha) * np.asarray(W @ sent.T).T * inv[None, :]
+    est = np.zeros((k, t))
+    for i, Fi in enumerate(leaves):
+        Fi = np.asarray(Fi, dtype=np.int64)
+        est[i, :] = node_est[:, Fi].sum(axis=1) / Fi.size
+    return est, R, node_est, rounds, active
+
+
+def gbp_error_term(ppr, leaves, targets, R, d):
+    """The error of the backward estimate for every (i, target c):
+        sum_{v_s in F(V_i)} d(v_s) / |F(V_i)| sum_{v_k} pi(v_s, v_k) r(v_k, V_j),
+    with ``ppr`` the exact n x n PPR matrix (rows = sources) and R the
+    len(targets) x n residue (the backward form of the push invariant)."""
+    d = np.asarray(d, dtype=np.float64)
+    out = np.zeros((len(leaves), len(targets)))
+    PR = ppr @ np.asarray(R).T  # n x t
+    for i, Fi in enumerate(leaves):
+        Fi = np.asarray(Fi, dtype=np.int64)
+        out[i, :] = (d[Fi][:, None] * PR[Fi, :]).sum(axis=0) / Fi.size
+    return out
+
+
+def dnpr(pi_d, leaves, m):
+    """Degree-normalized PageRank of each supernode (Eq. eq:dnpr-dnppr):
+    tau_j = sum_{v_t in F(V_j)} sum_{v_k} pi_d(v_k, v_t) / (m |F(V_j)|)."""
+    return np.array([pi_d[:, np.asarray(F, dtype=np.int64)].sum() / (m * len(F)) for F in leaves])
+
+
+def rmax_backward(eps, delta, d, leaves, j):
+    """Backward residue threshold of target V_j (Eq. eq:brmax):
+    eps delta / max over the other supernodes V_i of their mean leaf degree."""
+    means = [np.asarray(d)[np.asarray(F, dtype=np.int64)].mean() for i, F in enumerate(leaves) if i != j]
+    return eps * delta / max(means) if means else math.inf
+
+
+def tau_push(W, leaves, alpha, eps, delta, max_rounds=100000, tau=None):
+    """Algorithm alg:taupush: tau = 1 / sqrt(k n) (unless given), forward
+    threshold by Eq. eq:rmax, the Group Forward-Push from every source
+    supernode; then, for each target supernode with DNPR tau_j > tau, the
+    Group Backward-Push with its threshold by Eq. eq:brmax replaces the
+    column pi_d(., V_j).  The pushes run in synchronous rounds.  m is the arc
+    count (nnz of W).  Returns (estimate k x k, the refined targets, tau)."""
+    W = sp.csr_matrix(W)
+    d = degrees(W)
+    n = d.shape[0]
+    k = len(leaves)
+    m = W.nnz
+    if tau is None:
+        tau = tau_default(k, n)
+    est, _, _, _, _ = group_forward_push_rounds(W, leaves, alpha, rmax_forward(eps, delta, m, tau), max_rounds)
+    # Eq. eq:dnpr-dnppr on an undirected graph: sum_k pi_d(k, t) = d(t), so
+    # tau_j is the mean leaf degree of V_j over m (the column sums of pi_d
+    # are checked against this in the pins)
+    tau_j = np.array([d[np.asarray(F, dtype=np.int64)].mean() / m for F in leaves])
+    targets = [j for j in range(k) if tau_j[j] > tau]
+    if targets:
+        rb = [rmax_backward(eps, delta, d, leaves, j) for j in targets]
+        eb, _, _, _, _ = group_backward_push_rounds(W, leaves, targets, alpha, rb, max_rounds)
+        est[:, targets] = eb
+    return est, targets, tau

@@ -246,3 +246,130 @@ def test_rounds_stop_with_isolated_nodes():
     pi_d, d = _pi_d_exact(W)
     L = O.level_dppr(pi_d, leaves)
     np.testing.assert_allclose(est + O.gfp_error_term(pi_d, leaves, R, d), L, rtol=1e-10, atol=1e-14)
+
+
+# ------------------------------------------------- backward push, DNPR, Tau-Push
+
+
+def _exact_ppr(W):
+    P = O.transition(W)
+    d = O.degrees(W)
+    ppr = O.ppr_closed_form(P, ALPHA)
+    return ppr, ppr * d[:, None], d
+
+
+def test_first_backward_push_of_the_example(golden_dir):
+    ex = json.load(open(os.path.join(golden_dir, "backward_push_example.json")))
+    arcs = np.array(ex["graph"]["arcs"])
+    W = O.weight_matrix(ex["graph"]["n"], arcs[:, 0], arcs[:, 1], directed=True)
+    leaves = [np.array([10]), np.array([5]), np.array([6])]
+    est, r, pushes = O.group_backward_push(W, leaves, 0, ex["alpha"], 1e-9, max_pushes=1)
+    assert pushes == 1 and r[10] == 0
+    assert abs(est[0] - ex["after_first_push"]["estimate_target"]) < 1e-12
+    for v, want in ex["after_first_push"]["residue"].items():
+        assert abs(r[int(v)] - want) < 1e-12
+    assert est[1] == 0 and est[2] == 0
+
+
+@pytest.mark.parametrize("case", ["directed", "weighted"])
+def test_backward_push_invariant_every_stop(case):
+    # pi_d(V_i, V_j) = estimate + sum_{s in F_i} d(s)/|F_i| sum_k pi(s, k) r(k)
+    if case == "directed":
+        W, leaves = _directed_case(seed=22)
+    else:
+        W, leaves = _sbm_case(seed=31, weighted=True)
+        leaves = _ragged_leaves(W.shape[0], 6)
+    ppr, pi_d, d = _exact_ppr(W)
+    L = O.level_dppr(pi_d, leaves)
+    for j in range(len(leaves)):
+        for cap in (0, 1, 9, 80, None):
+            est, r, _ = O.group_backward_push(W, leaves, j, ALPHA, 1e-4, max_pushes=cap)
+            err = O.gbp_error_term(ppr, leaves, [j], r[None, :], d)[:, 0]
+            np.testing.assert_allclose(est + err, L[:, j], rtol=1e-10, atol=1e-14)
+
+
+@pytest.mark.parametrize("rb_max", [1e-2, 1e-5])
+def test_backward_push_stops_within_bound(rb_max):
+    # Lemma lem:bpsn-correct: every r <= rb_max at the stop, and the error of
+    # pi_d(V_i, V_j) is at most rb_max * (mean degree of F(V_i))
+    W, leaves = _sbm_case(seed=32)
+    ppr, pi_d, d = _exact_ppr(W)
+    L = O.level_dppr(pi_d, leaves)
+    bound = rb_max * np.array([d[F].mean() for F in leaves])
+    for j in range(len(leaves)):
+        est, r, _ = O.group_backward_push(W, leaves, j, ALPHA, rb_max)
+        assert np.all(r <= rb_max)
+        gap = L[:, j] - est
+        assert np.all(gap >= -1e-13) and np.all(gap <= bound * (1 + 1e-9))
+    est, _, _ = O.group_backward_push(W, leaves, 1, ALPHA, 1e-15)
+    np.testing.assert_allclose(est, L[:, 1], rtol=1e-10)
+
+
+def test_backward_rounds_zero_threshold_and_invariant():
+    W, leaves = _sbm_case(seed=33, weighted=True)
+    n = W.shape[0]
+    leaves = _ragged_leaves(n, 7)
+    P = O.transition(W)
+    d = O.degrees(W)
+    targets = [0, 2, 3]
+    for T in (1, 4, 30):
+        ppr_T, _, _ = O.ppr_power_iteration(P, np.arange(n), ALPHA, fixed_iters=T)
+        want = O.level_dppr(ppr_T * d[:, None], leaves)[:, targets]
+        est, R, _, rounds, _ = O.group_backward_push_rounds(W, leaves, targets, ALPHA, 0.0, T)
+        assert rounds == T
+        np.testing.assert_allclose(est, want, rtol=1e-12, atol=1e-15)
+    ppr, pi_d, d = _exact_ppr(W)
+    L = O.level_dppr(pi_d, leaves)
+    th = [1e-3, 1e-5, 1e-7]
+    est, R, _, _, active = O.group_backward_push_rounds(W, leaves, targets, ALPHA, th, 10 ** 5)
+    assert active == 0
+    assert np.all(R <= np.array(th)[:, None])
+    err = O.gbp_error_term(ppr, leaves, targets, R, d)
+    np.testing.assert_allclose(est + err, L[:, targets], rtol=1e-10, atol=1e-14)
+
+
+def test_backward_rounds_on_a_directed_graph():
+    W, leaves = _directed_case(seed=23)
+    ppr, pi_d, d = _exact_ppr(W)
+    L = O.level_dppr(pi_d, leaves)
+    targets = [1, 3]
+    est, R, _, _, active = O.group_backward_push_rounds(W, leaves, targets, ALPHA, 1e-6, 10 ** 5)
+    assert active == 0
+    err = O.gbp_error_term(ppr, leaves, targets, R, d)
+    np.testing.assert_allclose(est + err, L[:, targets], rtol=1e-10, atol=1e-14)
+
+
+def test_dnpr_of_an_undirected_graph_is_the_mean_degree_over_m():
+    W, leaves = _sbm_case(seed=34, weighted=True)
+    leaves = _ragged_leaves(W.shape[0], 8)
+    _, pi_d, d = _exact_ppr(W)
+    m = W.nnz
+    tau = O.dnpr(pi_d, leaves, m)
+    np.testing.assert_allclose(tau, [d[F].mean() / m for F in leaves], rtol=1e-10)
+    # Eq. eq:brmax: eps delta over the largest mean degree of the other
+    # sets (for the set of largest mean degree, the second largest counts)
+    means = np.array([d[F].mean() for F in leaves])
+    j = int(np.argmax(means))
+    rb = O.rmax_backward(0.5, 0.1, d, leaves, j)
+    assert abs(rb - 0.05 / np.delete(means, j).max()) < 1e-15
+    assert rb > 0.05 / means.max()
+
+
+def test_tau_push_mixes_both_directions_within_eps_delta():
+    W, leaves = _sbm_case(seed=35, n=90, blocks=6)
+    ppr, pi_d, d = _exact_ppr(W)
+    L = O.level_dppr(pi_d, leaves)
+    m = W.nnz
+    tau_j = np.array([d[F].mean() / m for F in leaves])
+    tau = float(np.median(tau_j))  # half the targets refined backward
+    eps, delta = 1 - 1 / np.e, 1 / (10 * len(leaves))
+    est, targets, _ = O.tau_push(W, leaves, ALPHA, eps, delta, tau=tau)
+    assert 0 < len(targets) < len(leaves)
+    assert targets == [j for j in range(len(leaves)) if tau_j[j] > tau]
+    off = ~np.eye(len(leaves), dtype=bool)
+    gap = (L - est)[off]
+    assert np.all(gap >= -1e-13) and np.all(gap <= eps * delta)
+    # the refined columns are the backward rounds, the rest the forward rounds
+    fw, _, _, _, _ = O.group_forward_push_rounds(W, leaves, ALPHA, O.rmax_forward(eps, delta, m, tau), 10 ** 5)
+    rest = [j for j in range(len(leaves)) if j not in targets]
+    np.testing.assert_array_equal(est[:, rest], fw[:, rest])
