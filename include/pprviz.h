@@ -122,7 +122,8 @@ ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src,
  * Section 4.2 Algorithm alg:fwdpushsn, Eq. eq:rmax)
  * ---------------------------------------------------------------------- */
 
-/* Workspace bytes needed by gfp_level_dppr. */
+/* Workspace bytes needed by gfp_level_dppr, gbp_level_dppr and
+ * tau_push_level_dppr for k supernodes. */
 size_t gfp_workspace(const ppr_csr* g, int32_t k, int32_t max_rounds);
 
 /*
@@ -168,6 +169,48 @@ ppr_status gfp_level_dppr(const ppr_csr* g, const int32_t* leaf_ptr, const int32
                           int32_t k, int64_t n_leaves, float alpha, double r_max,
                           int32_t max_rounds, float* dppr_out, float* est_out, float* resid_out,
                           int32_t* rounds_out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * The backward counterpart (Algorithm alg:bwdpushsn), towards the target
+ * supernodes targets[0 .. n_targets) (device int32 ids in [0, k), each a
+ * column of its own), in the same synchronous rounds.  Residue r_j(v) starts
+ * at 1 / |F(V_j)| on the leaves of V_j; a pair with r_j(v) > rb_max[c]
+ * (device float[n_targets], the column's threshold, Eq. eq:brmax) adds
+ * alpha d(v) r_j(v) to its estimate e_j(v), sends (1 - alpha) r_j(v) w_uv /
+ * d(u) to each neighbour u and keeps 0.  Only the target columns of
+ * dppr_out are written: dppr_out[i*k + targets[c]] = sum over v in F(V_i) of
+ * e_j(v) / |F(V_i)|.  est_out / resid_out (float[n_targets * n] or NULL) give
+ * e and r per column.  After a normal stop every residue is at most its
+ * threshold and 0 <= pi_d(V_i, V_j) - dppr_out <= rb_max * (mean degree of
+ * F(V_i)) up to FP32 rounding (Lemma lem:bpsn-correct).  Leaf lists and
+ * targets are checked on the device first (PPR_EINVAL, nothing written).
+ * Other conventions as gfp_level_dppr.
+ */
+ppr_status gbp_level_dppr(const ppr_csr* g, const int32_t* leaf_ptr, const int32_t* leaf_idx,
+                          int32_t k, int64_t n_leaves, const int32_t* targets, int32_t n_targets,
+                          const float* rb_max, float alpha, int32_t max_rounds, float* dppr_out,
+                          float* est_out, float* resid_out, int32_t* rounds_out, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/*
+ * Tau-Push (Algorithm alg:taupush): tau = 1 / sqrt(k n) (or the given tau
+ * when > 0), the forward threshold r_max = eps delta / (m tau) of Eq. eq:rmax
+ * with m = nnz, the forward pushes from every source supernode, then for
+ * every target V_j whose DNPR tau_j (Eq. eq:dnpr-dnppr; on an undirected
+ * graph the mean leaf degree of V_j over m) exceeds tau, the backward pushes
+ * with the threshold of Eq. eq:brmax (eps delta over the largest mean leaf
+ * degree of the other supernodes) replace column j.  Every off-diagonal
+ * estimate is then within eps delta below the level-l DPPR, up to FP32
+ * rounding.  n_backward_out (HOST int32 or NULL): targets refined;
+ * rounds_out (HOST int32[2] or NULL): forward and backward rounds.
+ * Returns PPR_EINVAL for eps or delta not > 0 or not finite, a graph without
+ * arcs, or the conditions of gfp_level_dppr.
+ */
+ppr_status tau_push_level_dppr(const ppr_csr* g, const int32_t* leaf_ptr, const int32_t* leaf_idx,
+                               int32_t k, int64_t n_leaves, float alpha, double eps, double delta,
+                               double tau, int32_t max_rounds, float* dppr_out,
+                               int32_t* n_backward_out, int32_t* rounds_out, void* ws,
+                               size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * PDist (Definition def:pprdist, Eq. eq:pprdist)

@@ -45,6 +45,10 @@ _SIGS = {
     "gfp_workspace": (sz, [C.POINTER(ppr_csr), i32, i32]),
     "gfp_level_dppr": (C.c_int, [C.POINTER(ppr_csr), vp, vp, i32, i64, f32, f64, i32, vp, vp, vp,
                                  C.POINTER(i32), vp, sz, vp]),
+    "gbp_level_dppr": (C.c_int, [C.POINTER(ppr_csr), vp, vp, i32, i64, vp, i32, vp, f32, i32, vp, vp, vp,
+                                 C.POINTER(i32), vp, sz, vp]),
+    "tau_push_level_dppr": (C.c_int, [C.POINTER(ppr_csr), vp, vp, i32, i64, f32, f64, f64, f64, i32, vp,
+                                      C.POINTER(i32), C.POINTER(i32), vp, sz, vp]),
     "pdist": (C.c_int, [vp, i32, i64, vp, vp]),
     "pdist_backward": (C.c_int, [vp, vp, i32, i64, vp, vp]),
     "layout_workspace": (sz, [i32]),

@@ -54,6 +54,10 @@ struct GfpWs {
     int32_t* active;   // 1 when the round pushed anything
     int32_t* info;
     double* part;      // aggregation partials [k][chunks][ld]
+    int32_t* col_set;  // backward: the target supernode of each column
+    float* th_col;     // backward: the residue threshold of each column (ld entries)
+    double* set_mean;  // mean leaf degree of each supernode (Tau-Push)
+    int32_t* count;    // number of targets Tau-Push refines backward
 };
 
 inline int64_t gfp_ld(int32_t k) { return (int64_t)(k + kSlab - 1) / kSlab * kSlab; }
@@ -76,6 +80,10 @@ void gfp_ws_layout(Cursor& c, int32_t n, int32_t k, int32_t max_rounds, GfpWs* w
     t.active = c.template take<int32_t>((size_t)std::max(max_rounds, 1));
     t.info = c.template take<int32_t>(kGfpInfo);
     t.part = c.template take<double>((size_t)(k * gfp_chunks(n) * ld));
+    t.col_set = c.template take<int32_t>((size_t)k);
+    t.th_col = c.template take<float>((size_t)ld);
+    t.set_mean = c.template take<double>((size_t)k);
+    t.count = c.template take<int32_t>(1);
     if (w) *w = t;
 }
 
@@ -116,17 +124,123 @@ __global__ void gfp_wide_count_kernel(const int32_t* __restrict__ hist, int32_t*
     info[2] = hist[kDegKeys - 2 - kGfpWideDeg];
 }
 
-// Initial residues: d(v) / |F(V_i)| in column i at each leaf v of V_i.  A
-// leaf listed twice in one set receives its share twice.
-// Blocks (i, *) take the leaves of set i, 256 at a time.
+// Initial residues of column c, supernode i = col_set[c] (c itself when
+// col_set is null): forward d(v) / |F(V_i)|, backward 1 / |F(V_i)|, at each
+// leaf v of V_i.  A leaf listed twice in one set receives its share twice.
+// Blocks (c, *) take the leaves of that set, 256 at a time.
 __global__ void gfp_seed_kernel(const int32_t* __restrict__ leaf_ptr, const int32_t* __restrict__ leaf_idx,
-                                const float* __restrict__ deg, int32_t n, float* __restrict__ resid) {
-    const int i = blockIdx.x;
+                                const float* __restrict__ deg, int32_t n, const int32_t* __restrict__ col_set,
+                                int backward, float* __restrict__ resid) {
+    const int c = blockIdx.x;
+    const int i = col_set ? col_set[c] : c;
     const int b = leaf_ptr[i], e = leaf_ptr[i + 1];
     for (int p = b + (int)blockIdx.y * 256 + (int)threadIdx.x; p < e; p += (int)gridDim.y * 256) {
         const int32_t v = leaf_idx[p];
-        atomicAdd(&resid[sidx(v, i, n)], deg[v] / (float)(e - b));
+        atomicAdd(&resid[sidx(v, c, n)], (backward ? 1.0f : deg[v]) / (float)(e - b));
     }
+}
+
+// Mean leaf degree of each supernode, in FP64 (one block per set).
+__global__ __launch_bounds__(256) void gfp_set_mean_kernel(const int32_t* __restrict__ leaf_ptr,
+                                                           const int32_t* __restrict__ leaf_idx,
+                                                           const float* __restrict__ deg,
+                                                           double* __restrict__ set_mean) {
+    __shared__ double red[256];
+    const int i = blockIdx.x;
+    const int b = leaf_ptr[i], e = leaf_ptr[i + 1];
+    double s = 0.0;
+    for (int p = b + (int)threadIdx.x; p < e; p += 256) s += (double)deg[leaf_idx[p]];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) set_mean[i] = red[0] / (double)(e - b);
+}
+
+// Tau-Push's choice of targets (one block of 1024): on an undirected graph
+// the DNPR of Eq. eq:dnpr-dnppr is tau_j = (mean leaf degree of V_j) / m,
+// since the DPPR column sums are the degrees; every V_j with tau_j > tau is
+// listed, in increasing j, with its backward threshold of Eq. eq:brmax,
+// eps delta over the largest mean leaf degree among the other supernodes.
+__global__ __launch_bounds__(1024) void tau_select_kernel(const double* __restrict__ set_mean, int32_t k, double m,
+                                                          double tau, double eps_delta,
+                                                          int32_t* __restrict__ col_set, float* __restrict__ th_col,
+                                                          int32_t* __restrict__ count) {
+    __shared__ double top[1024][2];
+    __shared__ int arg[1024];
+    __shared__ int scan[1024];
+    // largest and second largest mean (ties: the lower index is the largest)
+    double m1 = -1.0, m2 = -1.0;
+    int a1 = -1;
+    for (int j = threadIdx.x; j < k; j += 1024) {
+        const double x = set_mean[j];
+        if (x > m1) {
+            m2 = m1;
+            m1 = x;
+            a1 = j;
+        } else if (x > m2) {
+            m2 = x;
+        }
+    }
+    top[threadIdx.x][0] = m1;
+    top[threadIdx.x][1] = m2;
+    arg[threadIdx.x] = a1;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const double x1 = top[threadIdx.x][0], x2 = top[threadIdx.x][1];
+            const double y1 = top[threadIdx.x + o][0], y2 = top[threadIdx.x + o][1];
+            const int ax = arg[threadIdx.x], ay = arg[threadIdx.x + o];
+            const bool xfirst = x1 > y1 || (x1 == y1 && ax >= 0 && (ay < 0 || ax < ay));
+            top[threadIdx.x][0] = xfirst ? x1 : y1;
+            arg[threadIdx.x] = xfirst ? ax : ay;
+            top[threadIdx.x][1] = xfirst ? fmax(x2, y1) : fmax(y2, x1);
+        }
+        __syncthreads();
+    }
+    const double best = top[0][0], second = top[0][1];
+    const int best_j = arg[0];
+    int base = 0;
+    for (int j0 = 0; j0 < k; j0 += 1024) {
+        const int j = j0 + (int)threadIdx.x;
+        const bool pick = j < k && set_mean[j] / m > tau;
+        scan[threadIdx.x] = pick ? 1 : 0;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int x = (int)threadIdx.x >= o ? scan[threadIdx.x - o] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += x;
+            __syncthreads();
+        }
+        if (pick) {
+            const int pos = base + scan[threadIdx.x] - 1;
+            const double other = (j == best_j) ? second : best;
+            col_set[pos] = j;
+            th_col[pos] = other > 0.0 ? (float)(eps_delta / other) : 3.0e38f;
+        }
+        base += scan[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = base;
+}
+
+// Backward run of the standalone entry: columns take the caller's targets and
+// thresholds; info[0] flags a target outside [0, k).
+__global__ void gbp_columns_kernel(const int32_t* __restrict__ targets, const float* __restrict__ rb_max,
+                                   int32_t n_targets, int32_t k, int32_t* __restrict__ col_set,
+                                   float* __restrict__ th_col, int32_t* __restrict__ info) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_targets) return;
+    const int32_t j = targets[c];
+    if (j < 0 || j >= k) {
+        atomicOr(&info[0], 4);
+        col_set[c] = 0;
+    } else {
+        col_set[c] = j;
+    }
+    th_col[c] = rb_max[c];
 }
 
 struct GfpRound {
@@ -141,6 +255,7 @@ struct GfpRound {
     float* send_out;        // what this round pushes (SELECT)
     const uint8_t* flag_in; // which nodes pushed in the previous round, per slab (GATHER)
     uint8_t* flag_out;      // which nodes push in this round, per slab (SELECT)
+    const float* th_col;    // backward: the threshold of each column
     int32_t* active;        // active[t] = 1 when round t pushed anything
     int32_t n;
     int32_t wide;           // rows 0 .. wide-1 of the degree order have > kGfpWideDeg arcs
@@ -156,7 +271,11 @@ struct GfpRound {
 // neighbour keeps its residue, which the previous round left at or below
 // its threshold, and is skipped.  SELECT: push every pair over its
 // threshold (rounds t >= 0) and flag the rows that pushed.
-template <bool WEIGHTED, bool GATHER, bool SELECT>
+// BACKWARD (Algorithm alg:bwdpushsn, in the same rounds): the residue
+// arriving at v is (1 - alpha) / d(v) sum_u w_vu send[u] with send = r of the
+// pairs that pushed, the threshold is the column's own, and a push adds
+// alpha d(v) r to the estimate.
+template <bool WEIGHTED, bool GATHER, bool SELECT, bool BACKWARD>
 __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid grid) {
     if (a.t > 0 && a.active[a.t - 1] == 0) return;  // the previous round pushed nothing
     const int lane = threadIdx.x & 63;
@@ -212,22 +331,32 @@ __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid g
         float4* r4 = reinterpret_cast<float4*>(a.resid + off);
         float r[4] = {r4->x, r4->y, r4->z, r4->w};
         if (GATHER) {
-            const float keep = 1.0f - a.alpha;
+            const float keep = BACKWARD ? (1.0f - a.alpha) * a.invd[v] : 1.0f - a.alpha;
             r[0] += keep * acc.x;
             r[1] += keep * acc.y;
             r[2] += keep * acc.z;
             r[3] += keep * acc.w;
         }
         if (SELECT) {
-            const float th = a.deg[v] * a.r_max;
+            const float dv = a.deg[v];
+            float th[4];
+            if (BACKWARD) {
+                const float4 t4 = *reinterpret_cast<const float4*>(a.th_col + slab * kSlab + q * 4);
+                th[0] = t4.x;
+                th[1] = t4.y;
+                th[2] = t4.z;
+                th[3] = t4.w;
+            } else {
+                th[0] = th[1] = th[2] = th[3] = dv * a.r_max;
+            }
             const float id = a.invd[v];
             float s[4], add[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const bool on = r[c] > th;
+                const bool on = r[c] > th[c];
                 pushed += on ? 1 : 0;
-                s[c] = on ? r[c] * id : 0.f;
-                add[c] = on ? a.alpha * r[c] : 0.f;
+                s[c] = on ? (BACKWARD ? r[c] : r[c] * id) : 0.f;
+                add[c] = on ? (BACKWARD ? a.alpha * dv * r[c] : a.alpha * r[c]) : 0.f;
                 r[c] = on ? 0.f : r[c];
             }
             // what a row sends is read only when the row is flagged, i.e.
@@ -305,17 +434,32 @@ __global__ __launch_bounds__(256) void gfp_aggregate_kernel(const float* __restr
     }
 }
 
-// out[i][j] = (sum over chunks of part[j][chunk][i]) / |F(V_j)|.
+// Forward (col_set null, k columns): out[i][j] = (sum over chunks of
+// part[j][chunk][i]) / |F(V_j)|, the estimates of source column i summed over
+// the leaves of target V_j.  Backward: out[i][col_set[c]] = (sum over chunks
+// of part[i][chunk][c]) / |F(V_i)|, the estimates of target column c summed
+// over the leaves of source V_i.
 __global__ void gfp_finish_kernel(const double* __restrict__ part, const int32_t* __restrict__ leaf_ptr, int32_t k,
-                                  int64_t chunks, int64_t ld, float* __restrict__ out) {
+                                  int64_t chunks, int64_t ld, int32_t ncols, const int32_t* __restrict__ col_set,
+                                  float* __restrict__ out) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)k * k) return;
-    const int i = (int)(idx / k), j = (int)(idx % k);
-    const int64_t size = (int64_t)leaf_ptr[j + 1] - leaf_ptr[j];
+    if (idx >= (int64_t)k * ncols) return;
+    int set, col;
+    int64_t o;
+    if (col_set == nullptr) {
+        col = (int)(idx / k);
+        set = (int)(idx % k);
+        o = idx;
+    } else {
+        set = (int)(idx / ncols);
+        col = (int)(idx % ncols);
+        o = (int64_t)set * k + col_set[col];
+    }
+    const int64_t size = (int64_t)leaf_ptr[set + 1] - leaf_ptr[set];
     const int64_t used = (size + kGfpChunk - 1) / kGfpChunk;
     double t = 0.0;
-    for (int64_t ch = 0; ch < used; ++ch) t += part[((int64_t)j * chunks + ch) * ld + i];
-    out[idx] = (float)(t / (double)size);
+    for (int64_t ch = 0; ch < used; ++ch) t += part[((int64_t)set * chunks + ch) * ld + col];
+    out[o] = (float)(t / (double)size);
 }
 
 // out[i][v] = x[v][i] for i < k (slab layout -> row-major [k][n]), 64 x 64
@@ -347,12 +491,19 @@ StreamGrid gfp_grid(int32_t n, int32_t wide, int64_t ld) {
 }
 
 template <bool GATHER, bool SELECT>
-void gfp_launch_round(bool weighted, const GfpRound& a, const StreamGrid& g, hipStream_t s) {
+void gfp_launch_round(bool weighted, bool backward, const GfpRound& a, const StreamGrid& g, hipStream_t s) {
     const dim3 grid((unsigned)((int64_t)g.row_blocks * g.slabs));
-    if (weighted)
-        hipLaunchKernelGGL((gfp_round_kernel<true, GATHER, SELECT>), grid, dim3(256), 0, s, a, g);
-    else
-        hipLaunchKernelGGL((gfp_round_kernel<false, GATHER, SELECT>), grid, dim3(256), 0, s, a, g);
+    if (backward) {
+        if (weighted)
+            hipLaunchKernelGGL((gfp_round_kernel<true, GATHER, SELECT, true>), grid, dim3(256), 0, s, a, g);
+        else
+            hipLaunchKernelGGL((gfp_round_kernel<false, GATHER, SELECT, true>), grid, dim3(256), 0, s, a, g);
+    } else {
+        if (weighted)
+            hipLaunchKernelGGL((gfp_round_kernel<true, GATHER, SELECT, false>), grid, dim3(256), 0, s, a, g);
+        else
+            hipLaunchKernelGGL((gfp_round_kernel<false, GATHER, SELECT, false>), grid, dim3(256), 0, s, a, g);
+    }
 }
 
 ppr_status read_i32(const int32_t* dev, int32_t* host, size_t count, hipStream_t s) {
@@ -361,103 +512,117 @@ ppr_status read_i32(const int32_t* dev, int32_t* host, size_t count, hipStream_t
     return PPR_OK;
 }
 
-}  // namespace
+struct GfpArgs {
+    const ppr_csr* g;
+    const int32_t* leaf_ptr;
+    const int32_t* leaf_idx;
+    int32_t k;
+    int64_t n_leaves;
+    float alpha;
+    int32_t max_rounds;
+};
 
-}  // namespace pprviz
-
-using namespace pprviz;
-
-extern "C" {
-
-size_t gfp_workspace(const ppr_csr* g, int32_t k, int32_t max_rounds) {
-    if (g == nullptr || g->n < 1 || k < 1 || max_rounds < 1) return 0;
-    WsSize c;
-    gfp_ws_layout(c, g->n, k, max_rounds, nullptr);
-    return c.used;
-}
-
-ppr_status gfp_level_dppr(const ppr_csr* g, const int32_t* leaf_ptr, const int32_t* leaf_idx, int32_t k,
-                          int64_t n_leaves, float alpha, double r_max, int32_t max_rounds, float* dppr_out,
-                          float* est_out, float* resid_out, int32_t* rounds_out, void* ws, size_t ws_bytes,
-                          void* stream) {
-    ppr_status st = validate_csr(g);
+ppr_status gfp_validate(const GfpArgs& A, size_t ws_bytes, void* ws, GfpWs* w) {
+    ppr_status st = validate_csr(A.g);
     if (st != PPR_OK) return st;
-    if (k < 1 || leaf_ptr == nullptr || leaf_idx == nullptr || dppr_out == nullptr) return PPR_EINVAL;
-    if (n_leaves < k || n_leaves > (int64_t)k * g->n || n_leaves >= (int64_t)INT32_MAX) return PPR_EINVAL;
-    if (!(alpha > 0.0f && alpha < 1.0f) || !(r_max >= 0.0) || !std::isfinite(r_max) || max_rounds < 1)
+    if (A.k < 1 || A.leaf_ptr == nullptr || A.leaf_idx == nullptr) return PPR_EINVAL;
+    if (A.n_leaves < A.k || A.n_leaves > (int64_t)A.k * A.g->n || A.n_leaves >= (int64_t)INT32_MAX)
         return PPR_EINVAL;
-    if (g->n > kStreamMaxN) return PPR_EUNSUPPORTED;
+    if (!(A.alpha > 0.0f && A.alpha < 1.0f) || A.max_rounds < 1) return PPR_EINVAL;
+    if (A.g->n > kStreamMaxN) return PPR_EUNSUPPORTED;
     WsCursor cur{static_cast<char*>(ws), ws_bytes};
-    GfpWs w;
-    gfp_ws_layout(cur, g->n, k, max_rounds, &w);
+    gfp_ws_layout(cur, A.g->n, A.k, A.max_rounds, w);
     if (ws == nullptr || cur.used > ws_bytes) return PPR_EWORKSPACE;
     if (pending_error() != PPR_OK) return PPR_EHIP;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int32_t n = g->n;
-    const int64_t ld = gfp_ld(k);
+    return PPR_OK;
+}
 
-    // Leaf lists first: no output is written unless they are valid.
-    int32_t info[kGfpInfo] = {0, 0, 0, 0};
+// Checks the leaf lists (and the backward targets, when given), builds the
+// degrees and the degree row order, and reads back the check results, the
+// largest leaf set and the count of wide rows.  Nothing else is enqueued.
+ppr_status gfp_prepare(const GfpArgs& A, const GfpWs& w, const int32_t* targets, const float* rb_max,
+                       int32_t n_targets, int32_t info[kGfpInfo], hipStream_t s) {
+    const int32_t n = A.g->n;
     fill<int32_t>(w.info, 0, kGfpInfo, s);
-    hipLaunchKernelGGL(gfp_check_ptr_kernel, dim3((unsigned)((k + 256) / 256)), dim3(256), 0, s, leaf_ptr, k,
-                       n_leaves, n, w.info);
-    hipLaunchKernelGGL(gfp_check_idx_kernel, dim3((unsigned)std::min<int64_t>((n_leaves + 255) / 256, 4096)),
-                       dim3(256), 0, s, leaf_idx, n_leaves, n, w.info);
+    hipLaunchKernelGGL(gfp_check_ptr_kernel, dim3((unsigned)((A.k + 256) / 256)), dim3(256), 0, s, A.leaf_ptr,
+                       A.k, A.n_leaves, n, w.info);
+    hipLaunchKernelGGL(gfp_check_idx_kernel, dim3((unsigned)std::min<int64_t>((A.n_leaves + 255) / 256, 4096)),
+                       dim3(256), 0, s, A.leaf_idx, A.n_leaves, n, w.info);
+    if (targets) {
+        fill<float>(w.th_col, 3.0e38f, gfp_ld(A.k), s);
+        hipLaunchKernelGGL(gbp_columns_kernel, dim3((unsigned)((n_targets + 255) / 256)), dim3(256), 0, s, targets,
+                           rb_max, n_targets, A.k, w.col_set, w.th_col, w.info);
+    }
     // Row order by degree; the rows with more than kGfpWideDeg arcs come
     // first, and their count is read back with the check results.
-    launch_degree(g->row_ptr, g->weight, n, w.deg, w.invd, s);
-    stream_row_order(g->row_ptr, n, w.hist, w.rows, s);
+    launch_degree(A.g->row_ptr, A.g->weight, n, w.deg, w.invd, s);
+    stream_row_order(A.g->row_ptr, n, w.hist, w.rows, s);
     hipLaunchKernelGGL(gfp_wide_count_kernel, dim3(1), dim3(1), 0, s, w.hist, w.info);
-    if ((st = launch_status()) != PPR_OK) return st;
+    ppr_status st = launch_status();
+    if (st != PPR_OK) return st;
     if ((st = read_i32(w.info, info, kGfpInfo, s)) != PPR_OK) return st;
-    if (info[0] != 0) return PPR_EINVAL;
-    const int32_t wide = info[2];
+    return info[0] != 0 ? PPR_EINVAL : PPR_OK;
+}
 
+// One direction of pushes in rounds, from seeding to the k x k output.
+// Forward: k columns, column i the source supernode V_i, threshold
+// d(v) * r_max.  Backward: ncols columns, column c the target supernode
+// col_set[c] with threshold th_col[c] (both already in the workspace); only
+// the target columns of out are written.
+ppr_status gfp_run(const GfpArgs& A, const GfpWs& w, const int32_t info[kGfpInfo], bool backward, int32_t ncols,
+                   float r_max, float* dppr_out, float* est_out, float* resid_out, int32_t* rounds_out,
+                   bool* capped_out, hipStream_t s) {
+    const int32_t n = A.g->n;
+    const int32_t k = A.k;
+    const int64_t ld = gfp_ld(ncols);
+    const int32_t wide = info[2];
+    ppr_status st;
     fill<float>(w.resid, 0.f, n * ld, s);
     fill<float>(w.est, 0.f, n * ld, s);
-    fill<int32_t>(w.active, 0, max_rounds, s);
-    hipLaunchKernelGGL(gfp_seed_kernel, dim3((unsigned)k, (unsigned)std::min(4096, (info[1] + 255) / 256)),
-                       dim3(256), 0, s,
-                       leaf_ptr, leaf_idx, w.deg, n, w.resid);
+    fill<int32_t>(w.active, 0, A.max_rounds, s);
+    hipLaunchKernelGGL(gfp_seed_kernel, dim3((unsigned)ncols, (unsigned)std::min(4096, (info[1] + 255) / 256)),
+                       dim3(256), 0, s, A.leaf_ptr, A.leaf_idx, w.deg, n, backward ? w.col_set : nullptr,
+                       backward ? 1 : 0, w.resid);
 
-    const bool weighted = g->weight != nullptr;
+    const bool weighted = A.g->weight != nullptr;
     const StreamGrid grid = gfp_grid(n, wide, ld);
     GfpRound a;
     a.rows = w.rows;
-    a.col_idx = g->col_idx;
-    a.weight = g->weight;
+    a.col_idx = A.g->col_idx;
+    a.weight = A.g->weight;
     a.deg = w.deg;
     a.invd = w.invd;
     a.resid = w.resid;
     a.est = w.est;
     a.active = w.active;
+    a.th_col = w.th_col;
     a.n = n;
     a.wide = wide;
     a.wide_blocks = (wide + 3) / 4;
-    a.alpha = alpha;
-    a.r_max = (float)r_max;
+    a.alpha = A.alpha;
+    a.r_max = r_max;
     a.t = 0;
     a.send_in = nullptr;
     a.send_out = w.send[0];
     a.flag_in = nullptr;
     a.flag_out = w.flag[0];
-    gfp_launch_round<false, true>(weighted, a, grid, s);
+    gfp_launch_round<false, true>(weighted, backward, a, grid, s);
 
     // Rounds 1 .. max_rounds - 1 in growing batches; after each batch the
-    // host reads the last round's count and stops when it is zero.
+    // host reads the last round's flag and stops when it is clear.
     int32_t launched = 1, last = -1, batch = 4;
     while (true) {
         if ((st = launch_status()) != PPR_OK) return st;
         if ((st = read_i32(w.active + launched - 1, &last, 1, s)) != PPR_OK) return st;
-        if (last == 0 || launched == max_rounds) break;
-        const int32_t end = std::min(max_rounds, launched + batch);
+        if (last == 0 || launched == A.max_rounds) break;
+        const int32_t end = std::min(A.max_rounds, launched + batch);
         for (int32_t t = launched; t < end; ++t) {
             a.t = t;
             a.send_in = w.send[(t - 1) & 1];
             a.send_out = w.send[t & 1];
             a.flag_in = w.flag[(t - 1) & 1];
             a.flag_out = w.flag[t & 1];
-            gfp_launch_round<true, true>(weighted, a, grid, s);
+            gfp_launch_round<true, true>(weighted, backward, a, grid, s);
         }
         launched = end;
         batch = std::min(batch * 2, 64);
@@ -480,21 +645,119 @@ ppr_status gfp_level_dppr(const ppr_csr* g, const int32_t* leaf_ptr, const int32
         a.send_out = nullptr;
         a.flag_in = w.flag[(rounds - 1) & 1];
         a.flag_out = nullptr;
-        gfp_launch_round<true, false>(weighted, a, grid, s);
+        gfp_launch_round<true, false>(weighted, backward, a, grid, s);
     }
 
     const int64_t chunks = gfp_chunks(n);
     const int64_t used = ((int64_t)info[1] + kGfpChunk - 1) / kGfpChunk;
     hipLaunchKernelGGL(gfp_aggregate_kernel, dim3((unsigned)k, (unsigned)used), dim3(256), 0, s, w.est, n, ld,
-                       leaf_ptr, leaf_idx, chunks, w.part);
-    hipLaunchKernelGGL(gfp_finish_kernel, dim3((unsigned)(((int64_t)k * k + 255) / 256)), dim3(256), 0, s, w.part,
-                       leaf_ptr, k, chunks, ld, dppr_out);
-    const dim3 tgrid((unsigned)((n + 63) / 64), (unsigned)((k + 63) / 64));
-    if (est_out) hipLaunchKernelGGL(gfp_transpose_kernel, tgrid, dim3(256), 0, s, w.est, n, k, est_out);
-    if (resid_out) hipLaunchKernelGGL(gfp_transpose_kernel, tgrid, dim3(256), 0, s, w.resid, n, k, resid_out);
+                       A.leaf_ptr, A.leaf_idx, chunks, w.part);
+    hipLaunchKernelGGL(gfp_finish_kernel, dim3((unsigned)(((int64_t)k * ncols + 255) / 256)), dim3(256), 0, s,
+                       w.part, A.leaf_ptr, k, chunks, ld, ncols, backward ? w.col_set : nullptr, dppr_out);
+    const dim3 tgrid((unsigned)((n + 63) / 64), (unsigned)((ncols + 63) / 64));
+    if (est_out) hipLaunchKernelGGL(gfp_transpose_kernel, tgrid, dim3(256), 0, s, w.est, n, ncols, est_out);
+    if (resid_out) hipLaunchKernelGGL(gfp_transpose_kernel, tgrid, dim3(256), 0, s, w.resid, n, ncols, resid_out);
     if ((st = launch_status()) != PPR_OK) return st;
     if (rounds_out) *rounds_out = rounds;
+    if (capped_out) *capped_out = capped;
+    return PPR_OK;
+}
+
+}  // namespace
+
+}  // namespace pprviz
+
+using namespace pprviz;
+
+extern "C" {
+
+size_t gfp_workspace(const ppr_csr* g, int32_t k, int32_t max_rounds) {
+    if (g == nullptr || g->n < 1 || k < 1 || max_rounds < 1) return 0;
+    WsSize c;
+    gfp_ws_layout(c, g->n, k, max_rounds, nullptr);
+    return c.used;
+}
+
+ppr_status gfp_level_dppr(const ppr_csr* g, const int32_t* leaf_ptr, const int32_t* leaf_idx, int32_t k,
+                          int64_t n_leaves, float alpha, double r_max, int32_t max_rounds, float* dppr_out,
+                          float* est_out, float* resid_out, int32_t* rounds_out, void* ws, size_t ws_bytes,
+                          void* stream) {
+    if (!(r_max >= 0.0) || !std::isfinite(r_max) || dppr_out == nullptr) return PPR_EINVAL;
+    const GfpArgs A{g, leaf_ptr, leaf_idx, k, n_leaves, alpha, max_rounds};
+    GfpWs w;
+    ppr_status st = gfp_validate(A, ws_bytes, ws, &w);
+    if (st != PPR_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t info[kGfpInfo] = {0, 0, 0, 0};
+    if ((st = gfp_prepare(A, w, nullptr, nullptr, 0, info, s)) != PPR_OK) return st;
+    bool capped = false;
+    st = gfp_run(A, w, info, false, k, (float)r_max, dppr_out, est_out, resid_out, rounds_out, &capped, s);
+    if (st != PPR_OK) return st;
     return capped ? PPR_ENOCONV : PPR_OK;
+}
+
+ppr_status gbp_level_dppr(const ppr_csr* g, const int32_t* leaf_ptr, const int32_t* leaf_idx, int32_t k,
+                          int64_t n_leaves, const int32_t* targets, int32_t n_targets, const float* rb_max,
+                          float alpha, int32_t max_rounds, float* dppr_out, float* est_out, float* resid_out,
+                          int32_t* rounds_out, void* ws, size_t ws_bytes, void* stream) {
+    if (targets == nullptr || rb_max == nullptr || n_targets < 1 || n_targets > k || dppr_out == nullptr)
+        return PPR_EINVAL;
+    const GfpArgs A{g, leaf_ptr, leaf_idx, k, n_leaves, alpha, max_rounds};
+    GfpWs w;
+    ppr_status st = gfp_validate(A, ws_bytes, ws, &w);
+    if (st != PPR_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t info[kGfpInfo] = {0, 0, 0, 0};
+    if ((st = gfp_prepare(A, w, targets, rb_max, n_targets, info, s)) != PPR_OK) return st;
+    bool capped = false;
+    st = gfp_run(A, w, info, true, n_targets, 0.f, dppr_out, est_out, resid_out, rounds_out, &capped, s);
+    if (st != PPR_OK) return st;
+    return capped ? PPR_ENOCONV : PPR_OK;
+}
+
+ppr_status tau_push_level_dppr(const ppr_csr* g, const int32_t* leaf_ptr, const int32_t* leaf_idx, int32_t k,
+                               int64_t n_leaves, float alpha, double eps, double delta, double tau,
+                               int32_t max_rounds, float* dppr_out, int32_t* n_backward_out, int32_t* rounds_out,
+                               void* ws, size_t ws_bytes, void* stream) {
+    if (!(eps > 0.0) || !(delta > 0.0) || !std::isfinite(eps) || !std::isfinite(delta) || !std::isfinite(tau) ||
+        dppr_out == nullptr)
+        return PPR_EINVAL;
+    const GfpArgs A{g, leaf_ptr, leaf_idx, k, n_leaves, alpha, max_rounds};
+    GfpWs w;
+    ppr_status st = gfp_validate(A, ws_bytes, ws, &w);
+    if (st != PPR_OK) return st;
+    if (g->nnz < 1) return PPR_EINVAL;  // m = 0 leaves Eq. eq:rmax undefined
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t info[kGfpInfo] = {0, 0, 0, 0};
+    if ((st = gfp_prepare(A, w, nullptr, nullptr, 0, info, s)) != PPR_OK) return st;
+    // Algorithm alg:taupush: tau = 1 / sqrt(k n) unless given, r_max by
+    // Eq. eq:rmax with m = nnz (each undirected edge is two arcs)
+    const double m = (double)g->nnz;
+    const double t = tau > 0.0 ? tau : 1.0 / std::sqrt((double)k * (double)g->n);
+    const double r_max = eps * delta / (m * t);
+    bool capped_f = false, capped_b = false;
+    int32_t rounds[2] = {0, 0};
+    st = gfp_run(A, w, info, false, k, (float)r_max, dppr_out, nullptr, nullptr, &rounds[0], &capped_f, s);
+    if (st != PPR_OK) return st;
+    // targets with DNPR above tau, refined by the backward pushes
+    fill<float>(w.th_col, 3.0e38f, gfp_ld(k), s);
+    hipLaunchKernelGGL(gfp_set_mean_kernel, dim3((unsigned)k), dim3(256), 0, s, leaf_ptr, leaf_idx, w.deg,
+                       w.set_mean);
+    hipLaunchKernelGGL(tau_select_kernel, dim3(1), dim3(1024), 0, s, w.set_mean, k, m, t, eps * delta, w.col_set,
+                       w.th_col, w.count);
+    if ((st = launch_status()) != PPR_OK) return st;
+    int32_t nb = 0;
+    if ((st = read_i32(w.count, &nb, 1, s)) != PPR_OK) return st;
+    if (nb > 0) {
+        st = gfp_run(A, w, info, true, nb, 0.f, dppr_out, nullptr, nullptr, &rounds[1], &capped_b, s);
+        if (st != PPR_OK) return st;
+    }
+    if (n_backward_out) *n_backward_out = nb;
+    if (rounds_out) {
+        rounds_out[0] = rounds[0];
+        rounds_out[1] = rounds[1];
+    }
+    return (capped_f || capped_b) ? PPR_ENOCONV : PPR_OK;
 }
 
 }  // extern "C"

@@ -123,6 +123,67 @@ def gfp_level_dppr(g: Csr, leaves, alpha=0.15, r_max=0.0, max_rounds=10000, want
     return out, est, resid, rounds.value, st
 
 
+def _leaf_lists(leaves, dev):
+    if isinstance(leaves, tuple):
+        ptr, idx = leaves
+    else:
+        sizes = [len(F) for F in leaves]
+        ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+        idx = np.concatenate([np.asarray(F, dtype=np.int32) for F in leaves]) if leaves else np.zeros(0, np.int32)
+    ptr = torch.as_tensor(ptr, dtype=torch.int32, device=dev).contiguous()
+    idx = torch.as_tensor(idx, dtype=torch.int32, device=dev).contiguous()
+    return ptr, idx
+
+
+def gbp_level_dppr(g: Csr, leaves, targets, rb_max, alpha=0.15, max_rounds=10000, out=None, want_est=False,
+                   want_resid=False, allow_noconv=False):
+    """Group Backward-Push in rounds towards the target supernodes `targets`
+    with per-target thresholds `rb_max`.  Writes the target columns of `out`
+    (a [k, k] tensor, zeros when not given).  Returns (out, est [t, n] or None,
+    resid [t, n] or None, rounds, status)."""
+    dev = g.row_ptr.device
+    ptr, idx = _leaf_lists(leaves, dev)
+    k = int(ptr.numel()) - 1
+    tg = torch.as_tensor(targets, dtype=torch.int32, device=dev).contiguous()
+    th = torch.as_tensor(rb_max, dtype=torch.float32, device=dev).reshape(-1).expand(tg.numel()).contiguous()
+    t = int(tg.numel())
+    cg = g.c()
+    ws = _ws(L.lib().gfp_workspace(C.byref(cg), k, max_rounds), dev)
+    out = torch.zeros((k, k), dtype=torch.float32, device=dev) if out is None else out
+    est = torch.empty((t, g.n), dtype=torch.float32, device=dev) if want_est else None
+    resid = torch.empty((t, g.n), dtype=torch.float32, device=dev) if want_resid else None
+    rounds = C.c_int32()
+    st = L.lib().gbp_level_dppr(C.byref(cg), _ptr(ptr), _ptr(idx), k, int(idx.numel()), _ptr(tg), t, _ptr(th),
+                                alpha, max_rounds, _ptr(out), _ptr(est), _ptr(resid), C.byref(rounds), _ptr(ws),
+                                ws.numel(), _stream(dev))
+    allow = (L.PPR_OK, L.PPR_ENOCONV) if allow_noconv else (L.PPR_OK,)
+    L.check("gbp_level_dppr", st, allow)
+    return out, est, resid, rounds.value, st
+
+
+def tau_push_level_dppr(g: Csr, leaves, alpha=0.15, eps=1 - 1 / math.e, delta=None, tau=0.0, max_rounds=10000,
+                        allow_noconv=False):
+    """Tau-Push: forward pushes from every supernode, backward refinement of
+    the targets whose DNPR exceeds tau (1/sqrt(kn) when tau <= 0).  delta
+    defaults to 1/(10k).  Returns (dppr [k, k], targets refined, (forward
+    rounds, backward rounds), status)."""
+    dev = g.row_ptr.device
+    ptr, idx = _leaf_lists(leaves, dev)
+    k = int(ptr.numel()) - 1
+    delta = 1.0 / (10 * k) if delta is None else delta
+    cg = g.c()
+    ws = _ws(L.lib().gfp_workspace(C.byref(cg), k, max_rounds), dev)
+    out = torch.empty((k, k), dtype=torch.float32, device=dev)
+    nb = C.c_int32()
+    rounds = (C.c_int32 * 2)()
+    st = L.lib().tau_push_level_dppr(C.byref(cg), _ptr(ptr), _ptr(idx), k, int(idx.numel()), alpha, eps, delta,
+                                     tau, max_rounds, _ptr(out), C.byref(nb), rounds, _ptr(ws), ws.numel(),
+                                     _stream(dev))
+    allow = (L.PPR_OK, L.PPR_ENOCONV) if allow_noconv else (L.PPR_OK,)
+    L.check("tau_push_level_dppr", st, allow)
+    return out, nb.value, (rounds[0], rounds[1]), st
+
+
 def pdist(dppr: torch.Tensor, n_clamp: int):
     _require_cuda(dppr)
     k = dppr.shape[0]

@@ -236,3 +236,123 @@ def test_full_size_partition_of_a_million_nodes(ops):
     # an undirected graph's exact level-l DPPR is symmetric: the estimate is
     # within the bound of being so
     assert np.all(np.abs(got - got.T) <= np.maximum(bound[None, :], bound[:, None]) + tol)
+
+
+# ------------------------------------------------ backward push and Tau-Push
+
+
+def _exact_ppr(g):
+    W = O.weight_matrix(g.n, g.eu, g.ev, g.weight)
+    d = O.degrees(W)
+    ppr = O.ppr_closed_form(O.transition(W), ALPHA)
+    return W, ppr, ppr * d[:, None], d
+
+
+@pytest.mark.parametrize("n,blocks,k_ragged,weighted", [(600, 6, 0, False), (601, 5, 40, True)])
+def test_backward_zero_threshold_is_the_truncated_series(ops, n, blocks, k_ragged, weighted):
+    g, leaves = _case(n, blocks, weighted, synth.BASE_SEED + n + 1)
+    if k_ragged:
+        leaves = _ragged(n, k_ragged, synth.BASE_SEED + 4)
+    k = len(leaves)
+    targets = list(range(0, k, 2)) + ([k - 1] if (k - 1) % 2 else [])
+    W = O.weight_matrix(g.n, g.eu, g.ev, g.weight)
+    d = O.degrees(W)
+    P = O.transition(W)
+    csr = ops.Csr.from_graph(g, "cuda")
+    for T in (1, 3, 40):
+        print(f"[gbp zero] n={n} k={k} targets={len(targets)} T={T}", flush=True)
+        out, est, resid, rounds, _ = ops.gbp_level_dppr(csr, leaves, targets, 0.0, ALPHA, T, want_est=True,
+                                                         want_resid=True, allow_noconv=True)
+        assert rounds == T
+        ppr_T, _, _ = O.ppr_power_iteration(P, np.arange(n), ALPHA, fixed_iters=T)
+        want = O.level_dppr(ppr_T * d[:, None], leaves)[:, targets]
+        got = out.double().cpu().numpy()
+        assert np.abs(got[:, targets] - want).max() <= REL * np.abs(want).max()
+        others = [j for j in range(k) if j not in targets]
+        assert np.all(got[:, others] == 0)  # untouched columns of the zeroed output
+        e_o, R_o, ne_o, _, _ = O.group_backward_push_rounds(W, leaves, targets, ALPHA, 0.0, T)
+        assert np.abs(est.double().cpu().numpy() - ne_o).max() <= REL * np.abs(ne_o).max()
+        assert np.abs(resid.double().cpu().numpy() - R_o).max() <= REL * max(np.abs(R_o).max(), 1e-30)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_backward_result_is_valid(ops, weighted):
+    g, leaves = _case(1500, 8, weighted, synth.BASE_SEED + 19)
+    W, ppr, pi_d, d = _exact_ppr(g)
+    L = O.level_dppr(pi_d, leaves)
+    targets = [1, 4, 6]
+    th = np.array([1e-3, 1e-5, 1e-7])
+    csr = ops.Csr.from_graph(g, "cuda")
+    out, _, resid, _, _ = ops.gbp_level_dppr(csr, leaves, targets, th, ALPHA, 10000, want_resid=True)
+    got = out.double().cpu().numpy()[:, targets]
+    R = resid.double().cpu().numpy()
+    assert np.all(R <= th.astype(np.float32).astype(np.float64)[:, None] * (1 + 1e-6))
+    err = O.gbp_error_term(ppr, leaves, targets, R, d)
+    assert np.abs(got + err - L[:, targets]).max() <= REL * np.abs(L).max()
+    means = np.array([d[F].mean() for F in leaves])
+    bound = means[:, None] * th[None, :]
+    tol = REL * np.abs(L).max()
+    gap = L[:, targets] - got
+    assert np.all(gap >= -tol) and np.all(gap <= bound + tol)
+    e_o, _, _, _, _ = O.group_backward_push_rounds(W, leaves, targets, ALPHA, th, 10000)
+    assert np.all(np.abs(got - e_o) <= bound + tol)
+
+
+def test_invalid_backward_targets_are_rejected(ops):
+    from paper_2112_14944_amd import _lib
+    g, leaves = _case(200, 2, False, synth.BASE_SEED + 37)
+    csr = ops.Csr.from_graph(g, "cuda")
+    with pytest.raises(_lib.PprvizError) as ei:
+        ops.gbp_level_dppr(csr, leaves, [0, 2], 1e-6, ALPHA, 100)
+    assert ei.value.status == _lib.PPR_EINVAL
+
+
+@pytest.mark.parametrize("forced_tau", [True, False])
+def test_tau_push_within_eps_delta(ops, forced_tau):
+    # 90-node SBM, 6 blocks: with tau at the median DNPR half the targets are
+    # refined backward; with the paper's tau = 1/sqrt(kn) the choice follows
+    # the graph.  Every off-diagonal estimate lies within eps*delta below the
+    # exact level-l DPPR, and the refined set matches the oracle's.
+    g, leaves = _case(90, 6, False, synth.BASE_SEED + 41)
+    W, ppr, pi_d, d = _exact_ppr(g)
+    L = O.level_dppr(pi_d, leaves)
+    k = len(leaves)
+    eps, delta = 1 - 1 / np.e, 1 / (10 * k)
+    tau_j = np.array([d[F].mean() / g.nnz for F in leaves])
+    tau = float(np.median(tau_j)) if forced_tau else 0.0
+    csr = ops.Csr.from_graph(g, "cuda")
+    out, nb, rounds, _ = ops.tau_push_level_dppr(csr, leaves, ALPHA, eps, delta, tau)
+    est_o, targets, tau_o = O.tau_push(W, leaves, ALPHA, eps, delta, tau=tau if forced_tau else None)
+    assert nb == len(targets)
+    if forced_tau:
+        assert 0 < nb < k
+    got = out.double().cpu().numpy()
+    off = ~np.eye(k, dtype=bool)
+    tol = REL * np.abs(L).max()
+    gap = (L - got)[off]
+    assert np.all(gap >= -tol) and np.all(gap <= eps * delta + tol)
+    assert np.all(np.abs(got - est_o)[off] <= eps * delta + tol)
+
+
+def test_tau_push_refines_hub_supernodes_of_a_power_law_graph(ops):
+    # Chung-Lu n = 20000 (exponent 2.5, mean degree 20); 25 singleton
+    # supernodes at the 25 largest degrees: with the paper's tau = 1/sqrt(kn)
+    # the hubs whose DNPR d/m exceeds tau are refined backward.
+    g = synth.chung_lu(20000, 2.5, 20, synth.BASE_SEED + 2)
+    d = np.diff(g.row_ptr).astype(np.float64)
+    hubs = np.argsort(-d, kind="stable")[:25]
+    leaves = [np.array([h]) for h in hubs]
+    k = len(leaves)
+    tau = 1 / np.sqrt(k * g.n)
+    expect = int((d[hubs] / g.nnz > tau).sum())
+    csr = ops.Csr.from_graph(g, "cuda")
+    eps, delta = 1 - 1 / np.e, 1 / (10 * k)
+    out, nb, rounds, _ = ops.tau_push_level_dppr(csr, leaves, ALPHA, eps, delta)
+    assert nb == expect
+    W = O.weight_matrix(g.n, g.eu, g.ev)
+    est_o, targets, _ = O.tau_push(W, leaves, ALPHA, eps, delta)
+    assert len(targets) == expect
+    got = out.double().cpu().numpy()
+    off = ~np.eye(k, dtype=bool)
+    # both within eps*delta below the exact values, so within eps*delta of each other
+    assert np.all(np.abs(got - est_o)[off] <= eps * delta * (1 + 1e-4) + 1e-6 * np.abs(est_o).max())
