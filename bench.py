@@ -304,6 +304,77 @@ def gfp_cpu_oracle(g, k, r_max, sample=4):
                        f"{dt * sample / k:.1f} s, extrapolated linearly to {k}")
 
 
+def gbp_level(ops, dev, g, csr, k=25, reps=3):
+    """Level-l DPPR towards all 25 target supernodes of the top supernode of
+    the 10^6-node graph by the Group Backward-Push in rounds (one
+    gbp_level_dppr call), each target with its threshold of Eq. eq:brmax
+    (eps delta over the largest mean leaf degree of the other supernodes;
+    eps = 1 - 1/e, delta = 1/(10k)).  Same byte model per round as the
+    forward pushes."""
+    import torch
+    import synth
+
+    n = g.n
+    nnz = int(g.col_idx.shape[0])
+    sizes = synth.equal_blocks(n, k)
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    ptr = torch.as_tensor(starts.astype(np.int32), device=dev)
+    idx = torch.arange(n, dtype=torch.int32, device=dev)
+    deg = np.diff(g.row_ptr).astype(np.float64)
+    means = np.array([deg[starts[i]:starts[i + 1]].mean() for i in range(k)])
+    ed = (1.0 - 1.0 / math.e) / (10 * k)
+    th = np.array([ed / np.delete(means, j).max() for j in range(k)], dtype=np.float32)
+    best = None
+    rounds = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, _, _, rounds, _ = ops.gbp_level_dppr(csr, (ptr, idx), np.arange(k), th, ALPHA, 10000)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+    ld = 32 * ((k + 31) // 32)
+    alg = rounds * (16.0 * n * ld + 4.0 * nnz + 24.0 * n)
+    return dict(workload=f"chung_lu n={n} gamma=2.2 mean degree 30, k={k} target supernodes partitioning V, "
+                         f"thresholds by Eq. eq:brmax ({th.min():.3e} .. {th.max():.3e}), whole gbp_level_dppr call",
+                kernel="gfp_round_kernel (backward)", ms=best, rounds=rounds, bound="hbm", unit="GB/s",
+                achieved=alg / (best * 1e-3) / 1e9, peak=PEAK_HBM_GBS, frac=alg / (best * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                work=f"{alg:.4g} B over {rounds} rounds")
+
+
+def tau_push_hubs(ops, dev, reps=3):
+    """Tau-Push (Algorithm alg:taupush) on a supernode of 25 singleton
+    children at the 25 largest degrees of a Chung-Lu graph (n = 20000,
+    exponent 2.5, mean degree 20), with the paper's tau = 1/sqrt(kn),
+    eps = 1 - 1/e, delta = 1/(10k): the hubs whose DNPR exceeds tau are
+    refined by the backward pushes."""
+    import torch
+    import synth
+
+    g = synth.chung_lu(20000, 2.5, 20, synth.BASE_SEED + 2)
+    d = np.diff(g.row_ptr)
+    hubs = np.argsort(-d, kind="stable")[:25]
+    leaves = [np.array([h]) for h in hubs]
+    csr = ops.Csr.from_graph(g, dev)
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, nb, rounds, _ = ops.tau_push_level_dppr(csr, leaves, ALPHA)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+    return dict(workload="chung_lu n=20000 gamma=2.5 mean degree 20; 25 singleton supernodes at the largest "
+                         "degrees; tau = 1/sqrt(kn), eps 1-1/e, delta 1/(10k); whole tau_push_level_dppr call",
+                ms=best, backward_targets=nb, forward_rounds=rounds[0], backward_rounds=rounds[1])
+
+
 def gfp_level(ops, dev, g, csr, k=25, reps=3, cpu=False):
     """Level-l DPPR among the k = 25 children of the top supernode of the
     10^6-node Chung-Lu graph above, by Group Forward-Push in rounds (one
@@ -529,6 +600,8 @@ def main():
 
     spmm_big = None
     gfp = None
+    gbp = None
+    tau = None
     exact = None
     metrics = None
     if not args.no_spmm_large:
@@ -549,6 +622,12 @@ def main():
             gfp = gfp_level(ops, dev, g_big, csr_big, cpu=not args.no_cpu_baseline)
             log(f"level-l DPPR by group forward push (n = 10^6, k = 25): {gfp['ms']:.2f} ms, "
                 f"{gfp['rounds']} rounds, {gfp['achieved']:.0f} GB/s algorithmic")
+            gbp = gbp_level(ops, dev, g_big, csr_big)
+            log(f"level-l DPPR by group backward push (n = 10^6, 25 targets): {gbp['ms']:.2f} ms, "
+                f"{gbp['rounds']} rounds, {gbp['achieved']:.0f} GB/s algorithmic")
+            tau = tau_push_hubs(ops, dev)
+            log(f"Tau-Push, 25 hub supernodes (n = 20000): {tau['ms']:.2f} ms, {tau['backward_targets']} refined "
+                f"backward, rounds {tau['forward_rounds']} + {tau['backward_rounds']}")
         del g_big, csr_big
 
     cpu = None
@@ -582,6 +661,8 @@ def main():
         "spmm": spmm,
         "spmm_large": spmm_big,
         "level_dppr_gfp": gfp,
+        "level_dppr_gbp": gbp,
+        "tau_push": tau,
         "layout_exact": exact,
         "layout_metrics": metrics,
         "cpu_baseline": cpu,
