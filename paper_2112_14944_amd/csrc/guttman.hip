@@ -12,7 +12,9 @@
 //   update:     alpha = r.r / p.Ap;  x += alpha p;  r -= alpha Ap;  r.r
 //   direction:  beta = r.r(new) / r.r(old);  p = r + beta p;  stop test
 // Every dot product is summed in FP64 from per-block partials in a fixed
-// order, so the iterates do not depend on scheduling.  The apply is the
+// order, so the iterates do not depend on scheduling.  The host launches the
+// iterations in batches (8, then doubling) and reads the stop flag after each;
+// kernels launched after the flag is set return at once.  The apply is the
 // pairwise row sweep of the Jacobi step (4 rows per wave, lanes striding
 // over j, 4 columns of loads in flight); it reads Delta once, 4 k^2 bytes.
 #include <math.h>
@@ -346,10 +348,6 @@ ppr_status layout_step_exact(const float* delta, int32_t k, const float* x_in, f
     int32_t launched = 0, batch = 8;
     CgState hs{};
     while (true) {
-        if (launch_status() != PPR_OK) return PPR_EHIP;
-        PPRVIZ_HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-        PPRVIZ_HIP_TRY(hipStreamSynchronize(s));
-        if (hs.done || launched >= cg_max_iter) break;
         const int32_t end = std::min(cg_max_iter, launched + batch);
         for (int32_t it = launched; it < end; ++it) {
             hipLaunchKernelGGL((cg_rows_kernel<kCgApply>), dim3((unsigned)rb), dim3(256), 0, s, delta, k, w.p, w.ap,
@@ -360,6 +358,10 @@ ppr_status layout_step_exact(const float* delta, int32_t k, const float* x_in, f
                                tol2, w.r, w.p, w.st);
         }
         launched = end;
+        if (launch_status() != PPR_OK) return PPR_EHIP;
+        PPRVIZ_HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        PPRVIZ_HIP_TRY(hipStreamSynchronize(s));
+        if (hs.done || launched >= cg_max_iter) break;
         batch = std::min(batch * 2, 128);
     }
     if (cg_iters_out) *cg_iters_out = hs.iters;
