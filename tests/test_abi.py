@@ -89,6 +89,58 @@ def test_argument_validation_before_any_gpu_work(lib):
     assert lib.ppr_matrix_backward(None, 0.15, 10, None, None, None, None, 0, None) == L.PPR_EINVAL
 
 
+def test_validation_of_the_level_and_layout_entry_points(lib):
+    # every case returns before any GPU work
+    p = C.c_void_p(64)
+    ws = C.c_void_p(256)
+    g = L.ppr_csr(100, 400, p, p, None)
+    r = C.c_int32()
+    gfp = lib.gfp_level_dppr
+    assert gfp(C.byref(g), None, p, 3, 10, 0.15, 1e-6, 100, p, None, None, C.byref(r), ws, 1 << 30,
+               None) == L.PPR_EINVAL  # no leaf_ptr
+    assert gfp(C.byref(g), p, p, 0, 10, 0.15, 1e-6, 100, p, None, None, C.byref(r), ws, 1 << 30,
+               None) == L.PPR_EINVAL  # k < 1
+    assert gfp(C.byref(g), p, p, 3, 2, 0.15, 1e-6, 100, p, None, None, C.byref(r), ws, 1 << 30,
+               None) == L.PPR_EINVAL  # fewer leaves than sets
+    assert gfp(C.byref(g), p, p, 3, 10, 1.0, 1e-6, 100, p, None, None, C.byref(r), ws, 1 << 30,
+               None) == L.PPR_EINVAL  # alpha
+    assert gfp(C.byref(g), p, p, 3, 10, 0.15, -1.0, 100, p, None, None, C.byref(r), ws, 1 << 30,
+               None) == L.PPR_EINVAL  # r_max < 0
+    assert gfp(C.byref(g), p, p, 3, 10, 0.15, float("nan"), 100, p, None, None, C.byref(r), ws, 1 << 30,
+               None) == L.PPR_EINVAL
+    assert gfp(C.byref(g), p, p, 3, 10, 0.15, 1e-6, 0, p, None, None, C.byref(r), ws, 1 << 30,
+               None) == L.PPR_EINVAL  # max_rounds
+    assert gfp(C.byref(g), p, p, 3, 10, 0.15, 1e-6, 100, p, None, None, C.byref(r), ws, 16,
+               None) == L.PPR_EWORKSPACE
+    gbp = lib.gbp_level_dppr
+    assert gbp(C.byref(g), p, p, 3, 10, None, 2, p, 0.15, 100, p, None, None, C.byref(r), ws, 1 << 30,
+               None) == L.PPR_EINVAL  # no targets
+    assert gbp(C.byref(g), p, p, 3, 10, p, 4, p, 0.15, 100, p, None, None, C.byref(r), ws, 1 << 30,
+               None) == L.PPR_EINVAL  # more targets than sets
+    tau = lib.tau_push_level_dppr
+    for eps, delta in ((0.0, 0.1), (0.5, 0.0), (float("inf"), 0.1)):
+        assert tau(C.byref(g), p, p, 3, 10, 0.15, eps, delta, 0.0, 100, p, None, None, ws, 1 << 30,
+                   None) == L.PPR_EINVAL
+    assert lib.gfp_workspace(C.byref(g), 40, 100) > lib.gfp_workspace(C.byref(g), 3, 100) > 0
+    # exact majorization step and metrics
+    it = C.c_int32()
+    ex = lib.layout_step_exact
+    assert ex(p, 8, C.c_void_p(128), C.c_void_p(128), 1e-6, 10, C.byref(it), ws, 1 << 20, None) == L.PPR_EINVAL
+    assert ex(p, 8, C.c_void_p(128), C.c_void_p(256), -1.0, 10, C.byref(it), ws, 1 << 20, None) == L.PPR_EINVAL
+    assert ex(p, 8, C.c_void_p(128), C.c_void_p(256), 1e-6, -1, C.byref(it), ws, 1 << 20, None) == L.PPR_EINVAL
+    assert ex(p, 8, C.c_void_p(128), C.c_void_p(256), 1e-6, 10, C.byref(it), ws, 8, None) == L.PPR_EWORKSPACE
+    assert lib.layout_exact_workspace(4096) > lib.layout_exact_workspace(64) > 0
+    nd = C.c_double()
+    ul = C.c_double()
+    lm = lib.layout_metrics
+    assert lm(p, 8, None, None, None, ws, 1 << 20, None) == L.PPR_EINVAL  # nothing asked
+    assert lm(p, 8, None, C.byref(nd), C.byref(ul), ws, 1 << 20, None) == L.PPR_EINVAL  # ULCV needs a graph
+    g8 = L.ppr_csr(9, 4, p, p, None)
+    assert lm(p, 8, C.byref(g8), C.byref(nd), C.byref(ul), ws, 1 << 20, None) == L.PPR_EINVAL  # n != k
+    assert lm(p, 8, None, C.byref(nd), None, ws, 8, None) == L.PPR_EWORKSPACE
+    assert lib.layout_metrics_workspace(4096) > lib.layout_metrics_workspace(64) > 0
+
+
 def test_batch_validation_and_limits(lib):
     assert lib.pprviz_batch_max_n() == 2304
     p = C.c_void_p(64)
