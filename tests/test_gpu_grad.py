@@ -67,7 +67,7 @@ def test_gradients_against_central_differences(mods):
     assert np.abs(gx.ravel()[x_idx] - fd_x).max() <= 1e-3 * np.abs(gx).max()
 
 
-def test_c4_full_size_invariants_and_recompute(mods):
+def test_sbm_8192_weighted_invariants_and_recompute(mods):
     # n = 8192 SBM (32 blocks of 256, mean degree 24, 80% of edges inside
     # blocks), weights U[0.5, 2], T = 100.  Checks that hold at any size:
     # translation / rotation invariance of dL/dX, the weight-scaling Euler
@@ -76,7 +76,7 @@ def test_c4_full_size_invariants_and_recompute(mods):
     n = 8192
     g = synth.sbm(synth.equal_blocks(n, 32), 0.0753, 6.05e-4, synth.BASE_SEED + 3,
                   weighted=(0.5, 2.0, synth.BASE_SEED + 4))
-    print(f"[c4] n={n} nnz={g.nnz}", flush=True)
+    print(f"[sbm n=8192] n={n} nnz={g.nnz}", flush=True)
     X = synth.uniform_layout(n, synth.BASE_SEED + 5) * 20
     T = 100
     loss, gw, gx = _gpu_grads(ops, AG, g, X, T)

@@ -26,14 +26,14 @@ def ops():
     return get_ops()
 
 
-def test_c5_large_multi_source(ops):
+def test_million_node_graph_4096_sources(ops):
     g = synth.chung_lu(N, 2.2, 30, synth.BASE_SEED + 4)
     src = synth.random_sources(g, S, synth.BASE_SEED + 5)
-    print(f"[c5] n={g.n} nnz={g.nnz} sources={S}", flush=True)
+    print(f"[n=1e6] n={g.n} nnz={g.nnz} sources={S}", flush=True)
     csr = ops.Csr.from_graph(g, "cuda")
     ppr, dppr, T, resid = ops.ppr_matrix(csr, src, tgt=src, tol=1e-6, check_residual=True)
     torch.cuda.synchronize()
-    print("[c5] ppr done", flush=True)
+    print("[n=1e6] ppr done", flush=True)
     assert T == 86 and ppr.shape == (S, S)
     # residual over all 10^6 targets (FP64 sum of the FP32 iterate)
     assert np.abs(resid - (1 - ALPHA) ** 86).max() <= 2e-6
@@ -87,4 +87,4 @@ def test_c5_large_multi_source(ops):
             lr *= 0.5
         x, st = xn, min(st, sn)
     assert st <= st_l
-    print(f"[c5] stress {st0.item():.4e} -> {st_l:.4e} (200 sweeps) -> {st:.4e} (gradient)", flush=True)
+    print(f"[n=1e6] stress {st0.item():.4e} -> {st_l:.4e} (200 sweeps) -> {st:.4e} (gradient)", flush=True)

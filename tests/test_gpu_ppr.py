@@ -20,12 +20,12 @@ def _csr(ops, g):
     return ops.Csr.from_graph(g, "cuda")
 
 
-def test_c1_erdos_renyi_all_pairs(ops):
+def test_erdos_renyi_500_all_pairs(ops):
     # ER n=500, mean degree 8, all 500 sources, L1 residual 1e-10 (T = 142),
     # then PDist and 300 Jacobi layout steps from U[-1,1]^2.
     g = synth.erdos_renyi(500, 8, synth.BASE_SEED)
     src = np.arange(g.n)
-    print(f"[c1] n={g.n} nnz={g.nnz}", flush=True)
+    print(f"[er n=500] n={g.n} nnz={g.nnz}", flush=True)
     ppr, dppr, T, resid = ops.ppr_matrix(_csr(ops, g), src, tol=1e-10, check_residual=True)
     est, dppr_o, T_o, res_o, d = oracle_ppr(g, src, tol=1e-10)
     assert T == T_o == 142
@@ -198,14 +198,14 @@ def test_nonfinite_weights_reported(ops):
     assert ei.value.status == PPR_ENONFINITE
 
 
-def test_c2_chung_lu_all_pairs_sampled(ops):
+def test_chung_lu_20000_all_pairs_sampled(ops):
     # Chung-Lu n=20000, gamma 2.5, mean degree 20, all 20000 sources to L1
     # residual 1e-7 (T = 100): full FP32 n x n output; the oracle checks 40
     # sampled sources, their PDist block, and one Jacobi step of 40 sampled
     # rows of the full-size layout.
     g = synth.chung_lu(20000, 2.5, 20, synth.BASE_SEED + 2)
     n = g.n
-    print(f"[c2] n={n} nnz={g.nnz}", flush=True)
+    print(f"[chung-lu n=20000] n={n} nnz={g.nnz}", flush=True)
     csr = _csr(ops, g)
     ppr, dppr, T, resid = ops.ppr_matrix(csr, np.arange(n), tol=1e-7, check_residual=True)
     assert T == 100
