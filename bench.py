@@ -113,7 +113,10 @@ def stage_rooflines(gb, T, ms):
     symmetric, so a sweep needs one triangle of 1/Delta with its diagonal,
     2 n (n + 1) bytes, plus 20 n of positions in and out and weight sums per
     subgraph; the per-tile partial sums the sweep writes and reads back are
-    overhead, not counted."""
+    overhead, not counted.  The layout's FP32 work, by the convention of 15
+    FLOP per ordered pair (FMA = 2, rsq = 1; dx, dy 2, d^2 3, rsq 1, c 1, w 1,
+    w X_j 4, c (dx, dy) 4), is k (k - 1) * 15 per sweep and subgraph, reported
+    against the FP32 vector peak."""
     sizes = gb.sizes.astype(np.float64)
     nnz = np.diff(gb.row_ptr.astype(np.int64))
     arcs = np.add.reduceat(nnz, gb.node_off[:-1].astype(np.int64)).astype(np.float64)
@@ -132,6 +135,10 @@ def stage_rooflines(gb, T, ms):
                   unit="GB/s", achieved=layout_bytes / (lay_launch_ms * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
                   work=f"{layout_bytes:.4g} B per sweep (one triangle of 1/Delta, X in and out, weight sums)")
     st_lay["frac"] = st_lay["achieved"] / PEAK_HBM_GBS
+    lay_flops = STRESS_ITERS * 15.0 * float((sizes * (sizes - 1.0)).sum())
+    st_lay["flops"] = lay_flops
+    st_lay["tflops"] = lay_flops / (layout_ms * 1e-3) / 1e12
+    st_lay["flop_frac"] = st_lay["tflops"] / PEAK_FP32_TFLOPS
     return dict(plan_ms=ms[0], ppr=st_ppr, pdist_ms=ms[2], layout=st_lay)
 
 
@@ -529,7 +536,8 @@ def main():
                     unit=dom["unit"], frac=dom["frac"], traffic=traffic)
         log(f"stages ms: plan {ms[0]:.2f} ppr {ms[1]:.2f} pdist {ms[2]:.2f} layout {ms[3]:.2f}; "
             f"ppr {stages['ppr']['achieved']:.0f} GB/s ({stages['ppr']['adds_per_s'] / 1e12:.2f} T adds/s), "
-            f"layout {stages['layout']['achieved']:.0f} GB/s")
+            f"layout {stages['layout']['achieved']:.0f} GB/s, {stages['layout']['tflops']:.1f} TFLOP/s FP32 "
+            f"({100 * stages['layout']['flop_frac']:.0f}% of the vector peak)")
 
     # ---- plain path: one subgraph at a time through the C ABI
     plain = None
