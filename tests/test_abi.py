@@ -122,6 +122,9 @@ def test_validation_of_the_level_and_layout_entry_points(lib):
         assert tau(C.byref(g), p, p, 3, 10, 0.15, eps, delta, 0.0, 100, p, None, None, ws, 1 << 30,
                    None) == L.PPR_EINVAL
     assert lib.gfp_workspace(C.byref(g), 40, 100) > lib.gfp_workspace(C.byref(g), 3, 100) > 0
+    huge = L.ppr_csr((1 << 24) + 1, 400, p, p, None)  # beyond the 32-bit slab gather offsets
+    assert gfp(C.byref(huge), p, p, 3, 10, 0.15, 1e-6, 100, p, None, None, C.byref(r), ws, 1 << 62,
+               None) == L.PPR_EUNSUPPORTED
     # exact majorization step and metrics
     it = C.c_int32()
     ex = lib.layout_step_exact
