@@ -23,6 +23,14 @@
 // more than reading the arcs.  Round t sets a device flag when it pushed
 // anything; round t + 1 exits at once when round t pushed nothing, and the
 // host reads the flag every few rounds to stop launching.
+//
+// The same rounds run the Group Backward-Push (Algorithm alg:bwdpushsn):
+// column c is target supernode col_set[c], residues start at 1 / |F(V_j)|,
+// each column has its own absolute threshold (Eq. eq:brmax), what arrives at
+// v is scaled by 1 / d(v), and a push adds alpha d(v) r to the estimate.
+// Tau-Push (Algorithm alg:taupush) runs the forward rounds from every
+// source, picks the targets whose DNPR (Eq. eq:dnpr-dnppr) exceeds tau on
+// the device, and overwrites their columns with the backward rounds.
 #include <algorithm>
 #include <cmath>
 #include <vector>
