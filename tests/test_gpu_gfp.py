@@ -54,11 +54,12 @@ def _exact(g):
     return W, O.ppr_closed_form(O.transition(W), ALPHA) * d[:, None], d
 
 
-@pytest.mark.parametrize("n,blocks,k_ragged,weighted", [(600, 6, 0, False), (601, 5, 40, True), (97, 3, 0, False)])
+@pytest.mark.parametrize("n,blocks,k_ragged,weighted", [(600, 6, 0, False), (601, 5, 40, True), (97, 3, 0, False),
+                                                      (1203, 4, 70, False)])
 def test_zero_threshold_is_the_truncated_series(ops, n, blocks, k_ragged, weighted):
     g, leaves = _case(n, blocks, weighted, synth.BASE_SEED + n)
     if k_ragged:
-        leaves = _ragged(n, k_ragged, synth.BASE_SEED + 3)  # two slabs of columns
+        leaves = _ragged(n, k_ragged, synth.BASE_SEED + 3)  # two or three slabs of columns
     W = O.weight_matrix(g.n, g.eu, g.ev, g.weight)
     d = O.degrees(W)
     P = O.transition(W)
