@@ -355,7 +355,9 @@ def tau_push(W, leaves, alpha, eps, delta, max_rounds=100000, tau=None):
     # tau_j is the mean leaf degree of V_j over m (the column sums of pi_d
     # are checked against this in the pins)
     tau_j = np.array([d[np.asarray(F, dtype=np.int64)].mean() / m for F in leaves])
-    targets = [j for j in range(k) if tau_j[j] > tau]
+    # with one supernode, Eq. eq:brmax has no other supernode to take the
+    # maximum over: the column keeps its forward value
+    targets = [j for j in range(k) if tau_j[j] > tau] if k > 1 else []
     if targets:
         rb = [rmax_backward(eps, delta, d, leaves, j) for j in targets]
         eb, _, _, _, _ = group_backward_push_rounds(W, leaves, targets, alpha, rb, max_rounds)

@@ -213,7 +213,9 @@ __global__ __launch_bounds__(1024) void tau_select_kernel(const double* __restri
     int base = 0;
     for (int j0 = 0; j0 < k; j0 += 1024) {
         const int j = j0 + (int)threadIdx.x;
-        const bool pick = j < k && set_mean[j] / m > tau;
+        // with a single supernode there is no other one for Eq. eq:brmax:
+        // its column keeps the forward value
+        const bool pick = k > 1 && j < k && set_mean[j] / m > tau;
         scan[threadIdx.x] = pick ? 1 : 0;
         __syncthreads();
         for (int o = 1; o < 1024; o <<= 1) {

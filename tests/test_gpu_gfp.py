@@ -357,3 +357,21 @@ def test_tau_push_refines_hub_supernodes_of_a_power_law_graph(ops):
     off = ~np.eye(k, dtype=bool)
     # both within eps*delta below the exact values, so within eps*delta of each other
     assert np.all(np.abs(got - est_o)[off] <= eps * delta * (1 + 1e-4) + 1e-6 * np.abs(est_o).max())
+
+
+def test_degenerate_single_supernode(ops):
+    # k = 1: the level-l DPPR of a supernode with itself; forward rounds at
+    # r_max = 0 against the truncated series, and Tau-Push keeps the forward
+    # value (no other supernode for Eq. eq:brmax)
+    g, _ = _case(300, 3, False, synth.BASE_SEED + 43)
+    leaves = [np.arange(0, 300)]
+    W = O.weight_matrix(g.n, g.eu, g.ev)
+    csr = ops.Csr.from_graph(g, "cuda")
+    out, _, _, rounds, _ = ops.gfp_level_dppr(csr, leaves, ALPHA, 0.0, 9, allow_noconv=True)
+    e_o, _, _, _, _ = O.group_forward_push_rounds(W, leaves, ALPHA, 0.0, 9)
+    assert out.shape == (1, 1) and rounds == 9
+    assert abs(out.item() - e_o[0, 0]) <= REL * abs(e_o[0, 0])
+    tout, nb, _, _ = ops.tau_push_level_dppr(csr, leaves, ALPHA, 0.5, 0.05, tau=1e-12)
+    t_o, targets, _ = O.tau_push(W, leaves, ALPHA, 0.5, 0.05, tau=1e-12)
+    assert nb == 0 and targets == []
+    assert abs(tout.item() - t_o[0, 0]) <= REL * abs(t_o[0, 0])

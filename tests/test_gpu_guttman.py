@@ -116,3 +116,15 @@ def test_4096_node_layout_solves_its_system(ops):
     assert np.linalg.norm(res[:, 0]) <= 2e-5 * np.linalg.norm(rhs[:, 0])
     assert np.linalg.norm(res[:, 1]) <= 2e-5 * np.linalg.norm(rhs[:, 1])
     np.testing.assert_allclose(X.mean(axis=0), 0.0, atol=1e-5 * _scale(X))
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_exact_step_tiny_layouts(ops, k):
+    # k = 1: L^w = 0 and the centred solution is the origin; k = 2, 3: the
+    # pseudo-inverse solution of a tiny system
+    D = synth.random_distance_matrix(max(k, 2), synth.BASE_SEED + 80 + k)[:k, :k].copy()
+    Y = synth.uniform_layout(k, synth.BASE_SEED + 90 + k)
+    x, _ = ops.layout_step_exact(_t(D), _t(Y), cg_tol=CG_TOL)
+    want = O.majorization_step(Y.astype(np.float64), D.astype(np.float64))
+    got = x.double().cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-4 * max(_scale(want), 1e-30) + 1e-7

@@ -61,3 +61,10 @@ def test_metrics_of_a_computed_layout(ops):
     X = x.double().cpu().numpy()
     assert abs(nd - O.node_distribution(X)) <= 1e-9 * nd
     assert abs(ul - O.ulcv(X, g.eu, g.ev)) <= 1e-9 * ul
+
+
+def test_metrics_single_point(ops):
+    x = torch.zeros((1, 2), dtype=torch.float32, device="cuda")
+    g = synth.build_graph(1, np.zeros(0, np.int64), np.zeros(0, np.int64))
+    nd, ul = ops.layout_metrics(x, ops.Csr.from_graph(g, "cuda"))
+    assert nd == 0.0 and math.isnan(ul)

@@ -373,3 +373,12 @@ def test_tau_push_mixes_both_directions_within_eps_delta():
     fw, _, _, _, _ = O.group_forward_push_rounds(W, leaves, ALPHA, O.rmax_forward(eps, delta, m, tau), 10 ** 5)
     rest = [j for j in range(len(leaves)) if j not in targets]
     np.testing.assert_array_equal(est[:, rest], fw[:, rest])
+
+
+def test_tau_push_single_supernode_keeps_the_forward_value():
+    W, _ = _sbm_case(seed=36, n=40, blocks=2)
+    leaves = [np.arange(0, 40)]
+    est, targets, _ = O.tau_push(W, leaves, ALPHA, 0.5, 0.05, tau=1e-12)
+    assert targets == []
+    fw, _, _, _, _ = O.group_forward_push_rounds(W, leaves, ALPHA, O.rmax_forward(0.5, 0.05, W.nnz, 1e-12), 10 ** 5)
+    np.testing.assert_array_equal(est, fw)
