@@ -375,3 +375,21 @@ def test_degenerate_single_supernode(ops):
     t_o, targets, _ = O.tau_push(W, leaves, ALPHA, 0.5, 0.05, tau=1e-12)
     assert nb == 0 and targets == []
     assert abs(tout.item() - t_o[0, 0]) <= REL * abs(t_o[0, 0])
+
+
+def test_overlapping_and_repeated_leaves(ops):
+    # leaf lists that share a node and list a node twice: every formula reads
+    # F(V_i) as the given list, so the repeated node counts twice
+    g, _ = _case(200, 2, True, synth.BASE_SEED + 47)
+    leaves = [np.array([0, 1, 1, 2, 150]), np.array([2, 3, 4]), np.array([199])]
+    W = O.weight_matrix(g.n, g.eu, g.ev, g.weight)
+    csr = ops.Csr.from_graph(g, "cuda")
+    for T in (1, 6):
+        out, est, resid, _, _ = ops.gfp_level_dppr(csr, leaves, ALPHA, 0.0, T, want_est=True, want_resid=True,
+                                                   allow_noconv=True)
+        e_o, R_o, ne_o, _, _ = O.group_forward_push_rounds(W, leaves, ALPHA, 0.0, T)
+        assert np.abs(out.double().cpu().numpy() - e_o).max() <= REL * np.abs(e_o).max()
+        assert np.abs(resid.double().cpu().numpy() - R_o).max() <= REL * np.abs(R_o).max()
+        bo, _, _, _, _ = ops.gbp_level_dppr(csr, leaves, [0, 1, 2], 0.0, ALPHA, T, allow_noconv=True)
+        b_o, _, _, _, _ = O.group_backward_push_rounds(W, leaves, [0, 1, 2], ALPHA, 0.0, T)
+        assert np.abs(bo.double().cpu().numpy() - b_o).max() <= REL * np.abs(b_o).max()
