@@ -144,6 +144,23 @@ def test_validation_of_the_level_and_layout_entry_points(lib):
     assert lib.layout_metrics_workspace(4096) > lib.layout_metrics_workspace(64) > 0
 
 
+def test_plain_c_client(lib, tmp_path):
+    # the header compiles as C99 and a C program links and calls the library
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    exe = str(tmp_path / "c_abi_check")
+    libdir = os.path.dirname(L.LIB_PATH)
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "c_abi_check.c"), "-o", exe, "-L", libdir, "-lpprviz",
+                    "-Wl,-rpath," + libdir, "-lm"], check=True)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.startswith("c abi ok")
+
+
 def test_batch_validation_and_limits(lib):
     assert lib.pprviz_batch_max_n() == 2304
     p = C.c_void_p(64)
