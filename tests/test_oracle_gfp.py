@@ -382,3 +382,33 @@ def test_tau_push_single_supernode_keeps_the_forward_value():
     assert targets == []
     fw, _, _, _, _ = O.group_forward_push_rounds(W, leaves, ALPHA, O.rmax_forward(0.5, 0.05, W.nnz, 1e-12), 10 ** 5)
     np.testing.assert_array_equal(est, fw)
+
+
+# ------------------------------------------------------- randomized invariants
+
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=25, deadline=None)
+@given(seed=st.integers(0, 10 ** 6), n=st.integers(6, 28), k=st.integers(1, 4),
+       r_exp=st.integers(2, 9), weighted=st.booleans())
+def test_random_graphs_both_directions_keep_their_invariants(seed, n, k, r_exp, weighted):
+    # random undirected graphs (possibly with isolated nodes), random leaf
+    # lists (possibly overlapping): forward and backward rounds at any
+    # threshold satisfy their invariants with the exact inverse
+    rng = np.random.default_rng(seed)
+    mask = np.triu(rng.random((n, n)) < 0.25, 1)
+    eu, ev = np.nonzero(mask)
+    w = rng.uniform(0.5, 2.0, eu.size) if weighted else None
+    W = O.weight_matrix(n, eu, ev, w)
+    leaves = [np.sort(rng.choice(n, size=int(rng.integers(1, n // 2 + 1)), replace=False)) for _ in range(k)]
+    ppr, pi_d, d = _exact_ppr(W)
+    L = O.level_dppr(pi_d, leaves)
+    r_max = 10.0 ** (-r_exp)
+    est, R, _, _, active = O.group_forward_push_rounds(W, leaves, ALPHA, r_max, 10 ** 5)
+    assert active == 0
+    np.testing.assert_allclose(est + O.gfp_error_term(pi_d, leaves, R, d), L, rtol=1e-9, atol=1e-12)
+    targets = list(range(k))
+    eb, Rb, _, _, active_b = O.group_backward_push_rounds(W, leaves, targets, ALPHA, r_max, 10 ** 5)
+    assert active_b == 0
+    np.testing.assert_allclose(eb + O.gbp_error_term(ppr, leaves, targets, Rb, d), L, rtol=1e-9, atol=1e-12)
