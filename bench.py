@@ -29,6 +29,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
+# Plain FP32 adds: 256 CUs x 64 lanes x 2.4 GHz, one add per lane and clock
+# (a CU issues one 64-lane VALU instruction per clock; no packed FP32).
+PEAK_FP32_ADDS = 256 * 64 * 2.4e9
 ALPHA = 0.15
 TOL = 1e-6
 STRESS_ITERS = 200
@@ -129,7 +132,8 @@ def stage_rooflines(gb, T, ms):
     st_ppr = dict(kernel="batch_ppr_kernel", ms=ppr_ms, launches=3, bound="hbm", unit="GB/s",
                   achieved=ppr_bytes / (ppr_ms * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
                   work=f"{ppr_bytes:.4g} B over {pushes} pushes (X read and written once per push, plus CSR)",
-                  adds_per_s=ppr_adds / (ppr_ms * 1e-3), adds=ppr_adds)
+                  adds_per_s=ppr_adds / (ppr_ms * 1e-3), adds=ppr_adds,
+                  alu_peak_adds_per_s=PEAK_FP32_ADDS, alu_frac=ppr_adds / (ppr_ms * 1e-3) / PEAK_FP32_ADDS)
     st_ppr["frac"] = st_ppr["achieved"] / PEAK_HBM_GBS
     st_lay = dict(kernel="batch_pair_kernel", ms=layout_ms, launches=2 * (STRESS_ITERS + 1), bound="hbm",
                   unit="GB/s", achieved=layout_bytes / (lay_launch_ms * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
