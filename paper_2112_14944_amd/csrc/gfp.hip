@@ -19,10 +19,14 @@
 // by degree, 8 rows side by side per wave, neighbour rows gathered as 128-byte
 // pieces.  Each round flags, per slab and node, the rows that pushed, and the
 // next round reads only flagged neighbours and skips rows that received
-// nothing, so the late rounds, in which few pairs still push, cost little
-// more than reading the arcs.  Round t sets a device flag when it pushed
-// anything; round t + 1 exits at once when round t pushed nothing, and the
-// host reads the flag every few rounds to stop launching.
+// nothing.  On large grids, in the late rounds, in which few pairs still
+// push, the pushing rows also mark the heads of their arcs (when no block of
+// the round before pushed along more than min(kGfpMarkArcs, half its arcs)),
+// and the next round skips the unmarked rows without reading their arcs; a
+// round that is over that cap anywhere leaves the next one to the flags
+// alone.  Round t sets a device flag when it pushed anything; round t + 1
+// exits at once when round t pushed nothing, and the host reads the flag
+// every few rounds to stop launching.
 //
 // The same rounds run the Group Backward-Push (Algorithm alg:bwdpushsn):
 // column c is target supernode col_set[c], residues start at 1 / |F(V_j)|,
@@ -49,6 +53,15 @@ constexpr int kGfpInfo = 4;      // [0] bad leaf lists, [1] largest leaf set, [2
 // round.
 constexpr int kGfpWideDeg = 256;
 static_assert(kGfpWideDeg + 2 <= kDegKeys, "wide rows must have degree classes of their own");
+// A block whose pushing rows hold more arcs than this, or more than half of
+// the block's arcs, in a round is over the mark cap: it writes no receive
+// marks for the next round and stops the marks of the round after.
+constexpr int kGfpMarkArcs = 2048;
+// Rounds write and use receive marks only when their grid holds more than
+// this many blocks (4 x the 2048 blocks of 256 threads that 256 CUs keep
+// resident): a round whose blocks all fit at once is bound by one block's
+// latency, which the marks lengthen, and its flag scan is short anyway.
+constexpr int64_t kGfpMarkMinBlocks = 8192;
 
 struct GfpWs {
     RowEnt* rows;
@@ -59,7 +72,9 @@ struct GfpWs {
     float* est;        // estimate per (node, column), slab layout
     float* send[2];    // r / d of the pairs that pushed, by round parity
     uint8_t* flag[2];  // per slab and node: pushed in that round, by round parity
+    uint8_t* recv[2];  // per slab and node: marked by a pushing neighbour, by round parity
     int32_t* active;   // 1 when the round pushed anything
+    int32_t* over;     // 1 when a block of the round was over the mark cap
     int32_t* info;
     double* part;      // aggregation partials [k][chunks][ld]
     int32_t* col_set;  // backward: the target supernode of each column
@@ -70,6 +85,8 @@ struct GfpWs {
 
 inline int64_t gfp_ld(int32_t k) { return (int64_t)(k + kSlab - 1) / kSlab * kSlab; }
 inline int64_t gfp_chunks(int32_t n) { return ((int64_t)n + kGfpChunk - 1) / kGfpChunk; }
+// 32-bit words of one receive-mark buffer (a byte per slab and node)
+inline int64_t gfp_recv_words(int32_t n, int64_t ld) { return ((int64_t)n * (ld / kSlab) + 3) / 4; }
 
 template <typename Cursor>
 void gfp_ws_layout(Cursor& c, int32_t n, int32_t k, int32_t max_rounds, GfpWs* w) {
@@ -85,7 +102,12 @@ void gfp_ws_layout(Cursor& c, int32_t n, int32_t k, int32_t max_rounds, GfpWs* w
     t.send[1] = c.template take<float>((size_t)(n * ld));
     t.flag[0] = c.template take<uint8_t>((size_t)(n * (ld / kSlab)));
     t.flag[1] = c.template take<uint8_t>((size_t)(n * (ld / kSlab)));
+    // both mark buffers in one piece of whole words, cleared by one fill
+    uint8_t* recv = reinterpret_cast<uint8_t*>(c.template take<uint32_t>((size_t)(2 * gfp_recv_words(n, ld))));
+    t.recv[0] = recv;
+    t.recv[1] = recv ? recv + 4 * gfp_recv_words(n, ld) : nullptr;
     t.active = c.template take<int32_t>((size_t)std::max(max_rounds, 1));
+    t.over = c.template take<int32_t>((size_t)std::max(max_rounds, 1));
     t.info = c.template take<int32_t>(kGfpInfo);
     t.part = c.template take<double>((size_t)(k * gfp_chunks(n) * ld));
     t.col_set = c.template take<int32_t>((size_t)k);
@@ -265,14 +287,18 @@ struct GfpRound {
     float* send_out;        // what this round pushes (SELECT)
     const uint8_t* flag_in; // which nodes pushed in the previous round, per slab (GATHER)
     uint8_t* flag_out;      // which nodes push in this round, per slab (SELECT)
+    uint8_t* recv_in;       // marks written by round p, taken and cleared here (GATHER)
+    uint8_t* recv_out;      // marks for the next round (SELECT)
     const float* th_col;    // backward: the threshold of each column
     int32_t* active;        // active[t] = 1 when round t pushed anything
+    int32_t* over;          // over[t] = 1 when some block of round t was over the mark cap
     int32_t n;
     int32_t wide;           // rows 0 .. wide-1 of the degree order have > kGfpWideDeg arcs
     int32_t wide_blocks;    // blocks of 4 wide rows (one per wave), ahead of the rest
     float alpha;
     float r_max;
-    int32_t t;
+    int32_t t;              // this round (SELECT)
+    int32_t p;              // the round whose sends are gathered (GATHER)
 };
 
 // One round.  GATHER: add (1 - alpha) sum_u w_vu send_in[u] to the kept
@@ -285,7 +311,7 @@ struct GfpRound {
 // arriving at v is (1 - alpha) / d(v) sum_u w_vu send[u] with send = r of the
 // pairs that pushed, the threshold is the column's own, and a push adds
 // alpha d(v) r to the estimate.
-template <bool WEIGHTED, bool GATHER, bool SELECT, bool BACKWARD>
+template <bool WEIGHTED, bool GATHER, bool SELECT, bool BACKWARD, bool MARKS>
 __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid grid) {
     if (a.t > 0 && a.active[a.t - 1] == 0) return;  // the previous round pushed nothing
     const int lane = threadIdx.x & 63;
@@ -300,6 +326,9 @@ __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid g
     const int ri = wide ? rb * 4 + wave
                         : a.wide + (rb - a.wide_blocks) * kStreamRowsPerBlock + wave * kStreamRowsPerWave + grp;
     const bool has_row = ri < (wide ? a.wide : n);
+    const int64_t flag_off = (int64_t)slab * n;
+    // the previous round's cap flag, read early (it decides the marks below)
+    const bool may_mark = SELECT && MARKS && a.t >= 1 && a.over[a.t - 1] == 0;
     int rs = 0, dg = 0, v = 0;
     if (has_row) {
         const RowEnt e = load_row(as_global(a.rows), ri);
@@ -308,7 +337,17 @@ __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid g
         v = e.v;
     }
     const uint32_t qoff = (uint32_t)q * 16u;
-    const int64_t flag_off = (int64_t)slab * n;
+    const int deg_row = dg;
+    if (GATHER && MARKS && a.p >= 1 && a.over[a.p - 1] == 0) {
+        // Round p marked the heads of its pushing rows' arcs (no block of
+        // round p - 1 was over the cap): take this row's mark and clear it
+        // for reuse.  When no block of round p was over the cap either, the
+        // marks are complete and, the arcs being symmetric, a row without one
+        // has no pushing neighbour.
+        const uint8_t mark = has_row ? a.recv_in[flag_off + v] : 0;
+        if (mark && (wide ? lane == 0 : q == 0)) a.recv_in[flag_off + v] = 0;
+        if (mark == 0 && a.over[a.p] == 0) dg = 0;
+    }
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     int got = 1;
     if (GATHER) {
@@ -395,11 +434,47 @@ __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid g
         for (int o = 1; o < kSlabVec; o <<= 1) row_pushed |= __shfl_xor(row_pushed, o, kWave);
         if (owner && q == 0) a.flag_out[flag_off + v] = row_pushed ? 1 : 0;
         __shared__ int block_pushed;
-        if (threadIdx.x == 0) block_pushed = 0;
+        __shared__ int block_arcs;  // arcs of the block's pushing rows
+        __shared__ int block_all;   // arcs of all the block's rows
+        if (threadIdx.x == 0) {
+            block_pushed = 0;
+            if (MARKS) {
+                block_arcs = 0;
+                block_all = 0;
+            }
+        }
         __syncthreads();
         if (pushed) block_pushed = 1;
+        if (MARKS && owner && q == 0) {
+            atomicAdd(&block_all, deg_row);
+            if (row_pushed) atomicAdd(&block_arcs, deg_row);
+        }
         __syncthreads();
         if (threadIdx.x == 0 && block_pushed) a.active[a.t] = 1;
+        if (MARKS) {
+            const int arcs = block_arcs;
+            const bool over = arcs > min(kGfpMarkArcs, block_all / 2);
+            if (threadIdx.x == 0 && over) a.over[a.t] = 1;
+            // Mark the heads of the pushing rows' arcs for the next round, when
+            // the previous round was under the cap everywhere (a round that
+            // follows a dense one is likely dense too, and its marks would go
+            // unused).
+            if (may_mark && arcs > 0 && !over && has_row) {
+                if (wide) {
+                    // the first lane group owns the row; the whole wave marks
+                    if (__shfl(row_pushed, 0, kWave))
+                        for (int j = lane; j < deg_row; j += kWave) {
+                            const int u = a.col_idx[rs + j];
+                            if ((unsigned)u < (unsigned)n) a.recv_out[flag_off + u] = 1;
+                        }
+                } else if (row_pushed) {
+                    for (int j = q; j < deg_row; j += kSlabVec) {
+                        const int u = a.col_idx[rs + j];
+                        if ((unsigned)u < (unsigned)n) a.recv_out[flag_off + u] = 1;
+                    }
+                }
+            }
+        }
     }
 }
 
@@ -500,20 +575,30 @@ StreamGrid gfp_grid(int32_t n, int32_t wide, int64_t ld) {
     return g;
 }
 
-template <bool GATHER, bool SELECT>
+template <bool GATHER, bool SELECT, bool MARKS>
 void gfp_launch_round(bool weighted, bool backward, const GfpRound& a, const StreamGrid& g, hipStream_t s) {
     const dim3 grid((unsigned)((int64_t)g.row_blocks * g.slabs));
     if (backward) {
         if (weighted)
-            hipLaunchKernelGGL((gfp_round_kernel<true, GATHER, SELECT, true>), grid, dim3(256), 0, s, a, g);
+            hipLaunchKernelGGL((gfp_round_kernel<true, GATHER, SELECT, true, MARKS>), grid, dim3(256), 0, s, a, g);
         else
-            hipLaunchKernelGGL((gfp_round_kernel<false, GATHER, SELECT, true>), grid, dim3(256), 0, s, a, g);
+            hipLaunchKernelGGL((gfp_round_kernel<false, GATHER, SELECT, true, MARKS>), grid, dim3(256), 0, s, a, g);
     } else {
         if (weighted)
-            hipLaunchKernelGGL((gfp_round_kernel<true, GATHER, SELECT, false>), grid, dim3(256), 0, s, a, g);
+            hipLaunchKernelGGL((gfp_round_kernel<true, GATHER, SELECT, false, MARKS>), grid, dim3(256), 0, s, a, g);
         else
-            hipLaunchKernelGGL((gfp_round_kernel<false, GATHER, SELECT, false>), grid, dim3(256), 0, s, a, g);
+            hipLaunchKernelGGL((gfp_round_kernel<false, GATHER, SELECT, false, MARKS>), grid, dim3(256), 0, s, a,
+                               g);
     }
+}
+
+template <bool GATHER, bool SELECT>
+void gfp_launch_round(bool weighted, bool backward, bool marks, const GfpRound& a, const StreamGrid& g,
+                      hipStream_t s) {
+    if (marks)
+        gfp_launch_round<GATHER, SELECT, true>(weighted, backward, a, g, s);
+    else
+        gfp_launch_round<GATHER, SELECT, false>(weighted, backward, a, g, s);
 }
 
 ppr_status read_i32(const int32_t* dev, int32_t* host, size_t count, hipStream_t s) {
@@ -590,12 +675,17 @@ ppr_status gfp_run(const GfpArgs& A, const GfpWs& w, const int32_t info[kGfpInfo
     fill<float>(w.resid, 0.f, n * ld, s);
     fill<float>(w.est, 0.f, n * ld, s);
     fill<int32_t>(w.active, 0, A.max_rounds, s);
+    const StreamGrid grid = gfp_grid(n, wide, ld);
+    const bool marks = (int64_t)grid.row_blocks * grid.slabs > kGfpMarkMinBlocks;
+    if (marks) {
+        fill<int32_t>(w.over, 0, A.max_rounds, s);
+        fill<uint32_t>(reinterpret_cast<uint32_t*>(w.recv[0]), 0u, 2 * gfp_recv_words(n, ld), s);
+    }
     hipLaunchKernelGGL(gfp_seed_kernel, dim3((unsigned)ncols, (unsigned)std::min(4096, (info[1] + 255) / 256)),
                        dim3(256), 0, s, A.leaf_ptr, A.leaf_idx, w.deg, n, backward ? w.col_set : nullptr,
                        backward ? 1 : 0, w.resid);
 
     const bool weighted = A.g->weight != nullptr;
-    const StreamGrid grid = gfp_grid(n, wide, ld);
     GfpRound a;
     a.rows = w.rows;
     a.col_idx = A.g->col_idx;
@@ -605,6 +695,7 @@ ppr_status gfp_run(const GfpArgs& A, const GfpWs& w, const int32_t info[kGfpInfo
     a.resid = w.resid;
     a.est = w.est;
     a.active = w.active;
+    a.over = w.over;
     a.th_col = w.th_col;
     a.n = n;
     a.wide = wide;
@@ -612,11 +703,14 @@ ppr_status gfp_run(const GfpArgs& A, const GfpWs& w, const int32_t info[kGfpInfo
     a.alpha = A.alpha;
     a.r_max = r_max;
     a.t = 0;
+    a.p = -1;
     a.send_in = nullptr;
     a.send_out = w.send[0];
     a.flag_in = nullptr;
     a.flag_out = w.flag[0];
-    gfp_launch_round<false, true>(weighted, backward, a, grid, s);
+    a.recv_in = nullptr;
+    a.recv_out = w.recv[0];
+    gfp_launch_round<false, true>(weighted, backward, marks, a, grid, s);
 
     // Rounds 1 .. max_rounds - 1 in growing batches; after each batch the
     // host reads the last round's flag and stops when it is clear.
@@ -628,11 +722,14 @@ ppr_status gfp_run(const GfpArgs& A, const GfpWs& w, const int32_t info[kGfpInfo
         const int32_t end = std::min(A.max_rounds, launched + batch);
         for (int32_t t = launched; t < end; ++t) {
             a.t = t;
+            a.p = t - 1;
             a.send_in = w.send[(t - 1) & 1];
             a.send_out = w.send[t & 1];
             a.flag_in = w.flag[(t - 1) & 1];
             a.flag_out = w.flag[t & 1];
-            gfp_launch_round<true, true>(weighted, backward, a, grid, s);
+            a.recv_in = w.recv[(t - 1) & 1];
+            a.recv_out = w.recv[t & 1];
+            gfp_launch_round<true, true>(weighted, backward, marks, a, grid, s);
         }
         launched = end;
         batch = std::min(batch * 2, 64);
@@ -651,11 +748,14 @@ ppr_status gfp_run(const GfpArgs& A, const GfpWs& w, const int32_t info[kGfpInfo
         // deliver what the last round sent, so that the residues and the
         // estimates satisfy the invariant
         a.t = 0;
+        a.p = rounds - 1;
         a.send_in = w.send[(rounds - 1) & 1];
         a.send_out = nullptr;
         a.flag_in = w.flag[(rounds - 1) & 1];
         a.flag_out = nullptr;
-        gfp_launch_round<true, false>(weighted, backward, a, grid, s);
+        a.recv_in = w.recv[(rounds - 1) & 1];
+        a.recv_out = nullptr;
+        gfp_launch_round<true, false>(weighted, backward, marks, a, grid, s);
     }
 
     const int64_t chunks = gfp_chunks(n);

@@ -393,3 +393,67 @@ def test_overlapping_and_repeated_leaves(ops):
         bo, _, _, _, _ = ops.gbp_level_dppr(csr, leaves, [0, 1, 2], 0.0, ALPHA, T, allow_noconv=True)
         b_o, _, _, _, _ = O.group_backward_push_rounds(W, leaves, [0, 1, 2], ALPHA, 0.0, T)
         assert np.abs(bo.double().cpu().numpy() - b_o).max() <= REL * np.abs(b_o).max()
+
+
+# ------------------------------------- receive marks (grids of > 8192 blocks)
+
+
+def _mark_case():
+    # SBM n = 10^5 (50 blocks, mean degree ~14, no row over 256 arcs) and
+    # k = 70 sets of 2 random leaves: 3 slabs of columns, 9375 blocks per
+    # round, so the rounds mark the rows their pushes reach; the pushes
+    # spread out from 140 seeds, so rounds 1-3 are under the mark cap.
+    n = 100_000
+    g = synth.sbm(synth.equal_blocks(n, 50), 12.0 / (n / 50), 2.0 / n, synth.BASE_SEED + 71)
+    rng = np.random.default_rng(synth.BASE_SEED + 72)
+    leaves = [np.sort(rng.choice(n, 2, replace=False)) for _ in range(70)]
+    return g, leaves
+
+
+def test_receive_marks_match_the_truncated_series(ops):
+    # r_max = 0: every round (and the delivery after the round cap) is
+    # compared element by element with the FP64 rounds, forward and backward
+    g, leaves = _mark_case()
+    W = O.weight_matrix(g.n, g.eu, g.ev, g.weight)
+    csr = ops.Csr.from_graph(g, "cuda")
+    targets = list(range(len(leaves)))
+    for T in (1, 2, 3, 5):
+        print(f"[gfp marks] forward T={T}", flush=True)
+        out, est, resid, rounds, _ = ops.gfp_level_dppr(csr, leaves, ALPHA, 0.0, T, want_est=True,
+                                                         want_resid=True, allow_noconv=True)
+        assert rounds == T
+        e_o, R_o, ne_o, _, _ = O.group_forward_push_rounds(W, leaves, ALPHA, 0.0, T)
+        assert np.abs(out.double().cpu().numpy() - e_o).max() <= REL * np.abs(e_o).max()
+        assert np.abs(est.double().cpu().numpy() - ne_o).max() <= REL * np.abs(ne_o).max()
+        assert np.abs(resid.double().cpu().numpy() - R_o).max() <= REL * np.abs(R_o).max()
+    for T in (2, 4):
+        print(f"[gfp marks] backward T={T}", flush=True)
+        bo, best, bres, rounds, _ = ops.gbp_level_dppr(csr, leaves, targets, 0.0, ALPHA, T, want_est=True,
+                                                       want_resid=True, allow_noconv=True)
+        assert rounds == T
+        b_o, bR_o, bne_o, _, _ = O.group_backward_push_rounds(W, leaves, targets, ALPHA, 0.0, T)
+        assert np.abs(bo.double().cpu().numpy() - b_o).max() <= REL * np.abs(b_o).max()
+        assert np.abs(best.double().cpu().numpy() - bne_o).max() <= REL * np.abs(bne_o).max()
+        assert np.abs(bres.double().cpu().numpy() - bR_o).max() <= REL * np.abs(bR_o).max()
+
+
+def test_receive_marks_keep_residue_and_stopping_rule(ops):
+    # r_max > 0 on the same grid: the late rounds, in which few pairs push,
+    # skip the unmarked rows.  A row skipped while it had residue arriving
+    # would lose that residue (residue + estimate would fall short of the
+    # seeds' mean degree) or leave it above the threshold.
+    g, leaves = _mark_case()
+    d = O.degrees(O.weight_matrix(g.n, g.eu, g.ev, g.weight))
+    csr = ops.Csr.from_graph(g, "cuda")
+    for r_max in (1e-5, 1e-7):
+        print(f"[gfp marks] r_max={r_max}", flush=True)
+        out, est, resid, rounds, _ = ops.gfp_level_dppr(csr, leaves, ALPHA, r_max, 10000, want_est=True,
+                                                         want_resid=True)
+        R = resid.double().cpu().numpy()
+        E = est.double().cpu().numpy()
+        assert np.all(R <= d[None, :] * r_max * (1 + 1e-5))
+        mass = R.sum(axis=1) + E.sum(axis=1)
+        want_mass = np.array([d[F].mean() for F in leaves])
+        assert np.abs(mass - want_mass).max() <= 1e-5 * want_mass.max(), rounds
+        agg = np.stack([E[:, F].sum(axis=1) / len(F) for F in leaves], axis=1)
+        assert np.abs(out.double().cpu().numpy() - agg).max() <= 1e-6 * np.abs(agg).max()
