@@ -21,10 +21,10 @@
 // next round reads only flagged neighbours and skips rows that received
 // nothing.  On large grids, in the late rounds, in which few pairs still
 // push, the pushing rows also mark the heads of their arcs (when no block of
-// the round before pushed along more than min(kGfpMarkArcs, half its arcs)),
-// and the next round skips the unmarked rows without reading their arcs; a
-// round that is over that cap anywhere leaves the next one to the flags
-// alone.  Round t sets a device flag when it pushed anything; round t + 1
+// the round before pushed along more than half its arcs, or more than
+// kGfpMarkArcs, kGfpMarkArcsWide for blocks of wide rows), and the next
+// round skips the unmarked rows without reading their arcs; a round that is
+// over that cap anywhere leaves the next one to the flags alone.  Round t sets a device flag when it pushed anything; round t + 1
 // exits at once when round t pushed nothing, and the host reads the flag
 // every few rounds to stop launching.
 //
@@ -57,6 +57,9 @@ static_assert(kGfpWideDeg + 2 <= kDegKeys, "wide rows must have degree classes o
 // the block's arcs, in a round is over the mark cap: it writes no receive
 // marks for the next round and stops the marks of the round after.
 constexpr int kGfpMarkArcs = 2048;
+// The cap for blocks of wide rows (one row per wave, each wave marking its
+// own row's arcs 256 at a time).
+constexpr int kGfpMarkArcsWide = 8192;
 // Rounds write and use receive marks only when their grid holds more than
 // this many blocks (4 x the 2048 blocks of 256 threads that 256 CUs keep
 // resident): a round whose blocks all fit at once is bound by one block's
@@ -453,7 +456,7 @@ __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid g
         if (threadIdx.x == 0 && block_pushed) a.active[a.t] = 1;
         if (MARKS) {
             const int arcs = block_arcs;
-            const bool over = arcs > min(kGfpMarkArcs, block_all / 2);
+            const bool over = arcs > min(wide ? kGfpMarkArcsWide : kGfpMarkArcs, block_all / 2);
             if (threadIdx.x == 0 && over) a.over[a.t] = 1;
             // Mark the heads of the pushing rows' arcs for the next round, when
             // the previous round was under the cap everywhere (a round that
@@ -463,9 +466,16 @@ __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid g
                 if (wide) {
                     // the first lane group owns the row; the whole wave marks
                     if (__shfl(row_pushed, 0, kWave))
-                        for (int j = lane; j < deg_row; j += kWave) {
-                            const int u = a.col_idx[rs + j];
-                            if ((unsigned)u < (unsigned)n) a.recv_out[flag_off + u] = 1;
+                        for (int j0 = 0; j0 < deg_row; j0 += 4 * kWave) {
+                            int u[4];
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const int j = j0 + r * kWave + lane;
+                                u[r] = j < deg_row ? a.col_idx[rs + j] : -1;
+                            }
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                if ((unsigned)u[r] < (unsigned)n) a.recv_out[flag_off + u[r]] = 1;
                         }
                 } else if (row_pushed) {
                     for (int j = q; j < deg_row; j += kSlabVec) {
