@@ -78,6 +78,7 @@ struct GfpWs {
     uint8_t* recv[2];  // per slab and node: marked by a pushing neighbour, by round parity
     int32_t* active;   // 1 when the round pushed anything
     int32_t* over;     // 1 when a block of the round was over the mark cap
+    int32_t* sparse;   // 1 when a block of the round pushed along fewer than 7/8 of its arcs
     int32_t* info;
     double* part;      // aggregation partials [k][chunks][ld]
     int32_t* col_set;  // backward: the target supernode of each column
@@ -111,6 +112,7 @@ void gfp_ws_layout(Cursor& c, int32_t n, int32_t k, int32_t max_rounds, GfpWs* w
     t.recv[1] = recv ? recv + 4 * gfp_recv_words(n, ld) : nullptr;
     t.active = c.template take<int32_t>((size_t)std::max(max_rounds, 1));
     t.over = c.template take<int32_t>((size_t)std::max(max_rounds, 1));
+    t.sparse = c.template take<int32_t>((size_t)std::max(max_rounds, 1));
     t.info = c.template take<int32_t>(kGfpInfo);
     t.part = c.template take<double>((size_t)(k * gfp_chunks(n) * ld));
     t.col_set = c.template take<int32_t>((size_t)k);
@@ -295,6 +297,7 @@ struct GfpRound {
     const float* th_col;    // backward: the threshold of each column
     int32_t* active;        // active[t] = 1 when round t pushed anything
     int32_t* over;          // over[t] = 1 when some block of round t was over the mark cap
+    int32_t* sparse;        // sparse[t] = 1 when some block of round t pushed along < 7/8 of its arcs
     int32_t n;
     int32_t wide;           // rows 0 .. wide-1 of the degree order have > kGfpWideDeg arcs
     int32_t wide_blocks;    // blocks of 4 wide rows (one per wave), ahead of the rest
@@ -332,6 +335,12 @@ __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid g
     const int64_t flag_off = (int64_t)slab * n;
     // the previous round's cap flag, read early (it decides the marks below)
     const bool may_mark = SELECT && MARKS && a.t >= 1 && a.over[a.t - 1] == 0;
+    // After a round that was dense in every block, this round also writes
+    // zeros for the rows that do not push, so that the next round can gather
+    // every neighbour without reading push flags (a zero piece adds +0.0 to a
+    // sum of non-negative terms, so the result does not change).
+    const bool zero_fill = SELECT && MARKS && a.t >= 1 && a.sparse[a.t - 1] == 0;
+    const bool flagless = GATHER && MARKS && a.p >= 1 && a.sparse[a.p - 1] == 0 && a.sparse[a.p] == 0;
     int rs = 0, dg = 0, v = 0;
     if (has_row) {
         const RowEnt e = load_row(as_global(a.rows), ri);
@@ -358,9 +367,13 @@ __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid g
         const __amdgpu_buffer_rsrc_t rin = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float*>(a.send_in + slab_off), 0, (int)slab_bytes, 0x00020000);
         if (wide) {
-            acc = slab_gather<WEIGHTED, true, kWave>(rin, a.col_idx, a.weight, rs + kSlabVec * grp,
-                                                     max(dg - kSlabVec * grp, 0), lane, qoff,
-                                                     a.flag_in + flag_off, &got);
+            if (flagless)
+                acc = slab_gather<WEIGHTED, false, kWave>(rin, a.col_idx, a.weight, rs + kSlabVec * grp,
+                                                          max(dg - kSlabVec * grp, 0), lane, qoff);
+            else
+                acc = slab_gather<WEIGHTED, true, kWave>(rin, a.col_idx, a.weight, rs + kSlabVec * grp,
+                                                         max(dg - kSlabVec * grp, 0), lane, qoff,
+                                                         a.flag_in + flag_off, &got);
             // add the 8 groups' sums (a fixed tree) into every group
 #pragma unroll
             for (int o = kSlabVec; o < kWave; o <<= 1) {
@@ -370,6 +383,8 @@ __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid g
                 acc.w += __shfl_xor(acc.w, o, kWave);
                 got |= __shfl_xor(got, o, kWave);
             }
+        } else if (flagless) {
+            acc = slab_gather<WEIGHTED, false>(rin, a.col_idx, a.weight, rs, dg, lane, qoff);
         } else {
             acc = slab_gather<WEIGHTED, true>(rin, a.col_idx, a.weight, rs, dg, lane, qoff, a.flag_in + flag_off,
                                               &got);
@@ -436,6 +451,9 @@ __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid g
 #pragma unroll
         for (int o = 1; o < kSlabVec; o <<= 1) row_pushed |= __shfl_xor(row_pushed, o, kWave);
         if (owner && q == 0) a.flag_out[flag_off + v] = row_pushed ? 1 : 0;
+        if (zero_fill && owner && !row_pushed)
+            *reinterpret_cast<float4*>(a.send_out + slab_off + (int64_t)v * kSlab + q * 4) =
+                make_float4(0.f, 0.f, 0.f, 0.f);
         __shared__ int block_pushed;
         __shared__ int block_arcs;  // arcs of the block's pushing rows
         __shared__ int block_all;   // arcs of all the block's rows
@@ -458,6 +476,7 @@ __global__ __launch_bounds__(256) void gfp_round_kernel(GfpRound a, StreamGrid g
             const int arcs = block_arcs;
             const bool over = arcs > min(wide ? kGfpMarkArcsWide : kGfpMarkArcs, block_all / 2);
             if (threadIdx.x == 0 && over) a.over[a.t] = 1;
+            if (threadIdx.x == 0 && 8 * (int64_t)arcs < 7 * (int64_t)block_all) a.sparse[a.t] = 1;
             // Mark the heads of the pushing rows' arcs for the next round, when
             // the previous round was under the cap everywhere (a round that
             // follows a dense one is likely dense too, and its marks would go
@@ -689,6 +708,7 @@ ppr_status gfp_run(const GfpArgs& A, const GfpWs& w, const int32_t info[kGfpInfo
     const bool marks = (int64_t)grid.row_blocks * grid.slabs > kGfpMarkMinBlocks;
     if (marks) {
         fill<int32_t>(w.over, 0, A.max_rounds, s);
+        fill<int32_t>(w.sparse, 0, A.max_rounds, s);
         fill<uint32_t>(reinterpret_cast<uint32_t*>(w.recv[0]), 0u, 2 * gfp_recv_words(n, ld), s);
     }
     hipLaunchKernelGGL(gfp_seed_kernel, dim3((unsigned)ncols, (unsigned)std::min(4096, (info[1] + 255) / 256)),
@@ -706,6 +726,7 @@ ppr_status gfp_run(const GfpArgs& A, const GfpWs& w, const int32_t info[kGfpInfo
     a.est = w.est;
     a.active = w.active;
     a.over = w.over;
+    a.sparse = w.sparse;
     a.th_col = w.th_col;
     a.n = n;
     a.wide = wide;

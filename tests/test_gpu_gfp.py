@@ -412,12 +412,17 @@ def _mark_case():
 
 def test_receive_marks_match_the_truncated_series(ops):
     # r_max = 0: every round (and the delivery after the round cap) is
-    # compared element by element with the FP64 rounds, forward and backward
+    # compared element by element with the FP64 rounds, forward and backward.
+    # The same grids switch to flag-free gathers after rounds dense in every
+    # block.
     g, leaves = _mark_case()
     W = O.weight_matrix(g.n, g.eu, g.ev, g.weight)
     csr = ops.Csr.from_graph(g, "cuda")
     targets = list(range(len(leaves)))
-    for T in (1, 2, 3, 5):
+    # from round 4 on every block pushes along nearly all its arcs: rounds 5
+    # and up write zeros for the rows that do not push, rounds 6 and up (and
+    # the delivery after the cap at T = 8) gather without push flags
+    for T in (1, 2, 3, 5, 8):
         print(f"[gfp marks] forward T={T}", flush=True)
         out, est, resid, rounds, _ = ops.gfp_level_dppr(csr, leaves, ALPHA, 0.0, T, want_est=True,
                                                          want_resid=True, allow_noconv=True)
