@@ -398,32 +398,34 @@ def test_overlapping_and_repeated_leaves(ops):
 # ------------------------------------- receive marks (grids of > 8192 blocks)
 
 
-def _mark_case():
+def _mark_case(weighted=False):
     # SBM n = 10^5 (50 blocks, mean degree ~14, no row over 256 arcs) and
     # k = 70 sets of 2 random leaves: 3 slabs of columns, 9375 blocks per
     # round, so the rounds mark the rows their pushes reach; the pushes
     # spread out from 140 seeds, so rounds 1-3 are under the mark cap.
     n = 100_000
-    g = synth.sbm(synth.equal_blocks(n, 50), 12.0 / (n / 50), 2.0 / n, synth.BASE_SEED + 71)
+    wt = (0.5, 2.0, synth.BASE_SEED + 73) if weighted else None
+    g = synth.sbm(synth.equal_blocks(n, 50), 12.0 / (n / 50), 2.0 / n, synth.BASE_SEED + 71, weighted=wt)
     rng = np.random.default_rng(synth.BASE_SEED + 72)
     leaves = [np.sort(rng.choice(n, 2, replace=False)) for _ in range(70)]
     return g, leaves
 
 
-def test_receive_marks_match_the_truncated_series(ops):
+@pytest.mark.parametrize("weighted", [False, True])
+def test_receive_marks_match_the_truncated_series(ops, weighted):
     # r_max = 0: every round (and the delivery after the round cap) is
     # compared element by element with the FP64 rounds, forward and backward.
     # The same grids switch to flag-free gathers after rounds dense in every
     # block.
-    g, leaves = _mark_case()
+    g, leaves = _mark_case(weighted)
     W = O.weight_matrix(g.n, g.eu, g.ev, g.weight)
-    csr = ops.Csr.from_graph(g, "cuda")
+    csr = ops.Csr.from_graph(g, "cuda", weighted=weighted)
     targets = list(range(len(leaves)))
     # from round 4 on every block pushes along nearly all its arcs: rounds 5
     # and up write zeros for the rows that do not push, rounds 6 and up (and
     # the delivery after the cap at T = 8) gather without push flags
     for T in (1, 2, 3, 5, 8):
-        print(f"[gfp marks] forward T={T}", flush=True)
+        print(f"[gfp marks] weighted={weighted} forward T={T}", flush=True)
         out, est, resid, rounds, _ = ops.gfp_level_dppr(csr, leaves, ALPHA, 0.0, T, want_est=True,
                                                          want_resid=True, allow_noconv=True)
         assert rounds == T
@@ -432,7 +434,7 @@ def test_receive_marks_match_the_truncated_series(ops):
         assert np.abs(est.double().cpu().numpy() - ne_o).max() <= REL * np.abs(ne_o).max()
         assert np.abs(resid.double().cpu().numpy() - R_o).max() <= REL * np.abs(R_o).max()
     for T in (2, 4):
-        print(f"[gfp marks] backward T={T}", flush=True)
+        print(f"[gfp marks] weighted={weighted} backward T={T}", flush=True)
         bo, best, bres, rounds, _ = ops.gbp_level_dppr(csr, leaves, targets, 0.0, ALPHA, T, want_est=True,
                                                        want_resid=True, allow_noconv=True)
         assert rounds == T
