@@ -19,14 +19,18 @@
 // by degree, 8 rows side by side per wave, neighbour rows gathered as 128-byte
 // pieces.  Each round flags, per slab and node, the rows that pushed, and the
 // next round reads only flagged neighbours and skips rows that received
-// nothing.  On large grids, in the late rounds, in which few pairs still
-// push, the pushing rows also mark the heads of their arcs (when no block of
-// the round before pushed along more than half its arcs, or more than
-// kGfpMarkArcs, kGfpMarkArcsWide for blocks of wide rows), and the next
-// round skips the unmarked rows without reading their arcs; a round that is
-// over that cap anywhere leaves the next one to the flags alone.  Round t sets a device flag when it pushed anything; round t + 1
-// exits at once when round t pushed nothing, and the host reads the flag
-// every few rounds to stop launching.
+// nothing.  On large grids, in the late rounds, in which few pairs still push,
+// the pushing rows also mark the heads of their arcs (when no block of the
+// round before pushed along more than half its arcs or kGfpMarkArcs,
+// kGfpMarkArcsWide for blocks of wide rows), and the next round skips the
+// unmarked rows without reading their arcs; a round that is over that cap
+// anywhere leaves the next one to the flags alone.  In the dense rounds of
+// large grids (every block of the round before pushed along at least 7/8 of
+// its arcs), the rows that do not push write zero sends, and the round after,
+// if dense as well, gathers every neighbour without reading push flags.  Round
+// t sets a device flag when it pushed anything; round t + 1 exits at once when
+// round t pushed nothing, and the host reads the flag every few rounds to stop
+// launching.
 //
 // The same rounds run the Group Backward-Push (Algorithm alg:bwdpushsn):
 // column c is target supernode col_set[c], residues start at 1 / |F(V_j)|,
