@@ -422,6 +422,29 @@ ppr_status pprviz_batch_plan_create(const ppr_batch* b, float alpha, double tol_
 ppr_status pprviz_batch_plan_launch(pprviz_batch_plan* plan, void* stream);
 void pprviz_batch_plan_destroy(pprviz_batch_plan* plan);
 
+/*
+ * The exact stress-majorization step of layout_step_exact (the appendix's
+ * Guttman transform, eq:pprlayout-leq) for every subgraph of a batch in one
+ * launch, one thread block per subgraph with its CG vectors on chip:
+ *   x_out_g = (L^w_g)^+ L^Y(x_in_g) x_in_g   for Delta_g = delta_pool[mat_off[g] ..],
+ * the k_g x k_g row-major PDist that pprviz_batch writes (positive off the
+ * diagonal, read only off it).  Same CG, stopping rule, FP32 arithmetic and
+ * fixed-order FP64 dot products as layout_step_exact; each subgraph stops on
+ * its own.  No workspace, no host synchronization.
+ *  x_in, x_out  device float[2*n_nodes], x_in != x_out (positions at node_off)
+ *  iters_out    device int32[n_graphs] or NULL: CG iterations of each subgraph
+ *               (-1 for a subgraph of size outside [1, pprviz_batch_max_n()])
+ *  converged_out device int32[n_graphs] or NULL: 1 when the subgraph met
+ *               cg_tol, 0 when it stopped at cg_max_iter (x_out holds the last
+ *               iterate) or was skipped
+ * Returns PPR_EINVAL for NULL b / arrays, x_in == x_out, cg_tol < 0 or not
+ * finite, cg_max_iter < 0, b->max_n < 1; PPR_EUNSUPPORTED when b->max_n
+ * exceeds pprviz_batch_max_n().
+ */
+ppr_status pprviz_batch_step_exact(const ppr_batch* b, const float* delta_pool, const float* x_in,
+                                   float* x_out, double cg_tol, int32_t cg_max_iter, int32_t* iters_out,
+                                   int32_t* converged_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

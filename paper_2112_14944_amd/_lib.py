@@ -66,6 +66,7 @@ _SIGS = {
     "pprviz_batch": (C.c_int, [C.POINTER(ppr_batch), f32, f64, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
     "pprviz_batch_profile": (C.c_int, [C.POINTER(ppr_batch), f32, f64, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp,
                                        C.POINTER(f64)]),
+    "pprviz_batch_step_exact": (C.c_int, [C.POINTER(ppr_batch), vp, vp, vp, f64, i32, vp, vp, vp]),
     "pprviz_batch_plan_create": (C.c_int, [C.POINTER(ppr_batch), f32, f64, i32, i32, vp, vp, vp, vp, vp, vp, sz,
                                            vp, C.POINTER(vp)]),
     "pprviz_batch_plan_launch": (C.c_int, [vp, vp]),

@@ -306,6 +306,173 @@ __global__ __launch_bounds__(256) void cg_direction_kernel(int32_t k, int32_t it
     }
 }
 
+
+// ---------------------------------------------------------------- batch form
+// The exact step for every subgraph of a batch in one launch: one block of
+// 1024 threads per subgraph runs the whole CG above with its vectors in LDS
+// (Y, x, r, p, Ap: 40 bytes per node, 92 KB at the largest subgraph).  Rows
+// are dealt to the 16 waves round-robin; each row's pair sums use the same
+// per-lane order and wave tree as cg_rows_kernel, the dot products are FP64
+// wave trees whose 16 wave sums are added in wave order.
+constexpr int kCgBatchMaxN = 2304;  // the batch's largest subgraph
+constexpr int kCgBatchThreads = 1024;
+constexpr int kCgBatchWaves = kCgBatchThreads / kWave;
+
+// Fixed-order block sum of two FP64 values per thread; every thread gets both.
+__device__ __forceinline__ void cg_batch_sum2(double& a, double& b, double (*red)[kCgBatchWaves]) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    __syncthreads();  // the previous sum's readers are done with red
+    if (lane == 0) {
+        red[0][wave] = a;
+        red[1][wave] = b;
+    }
+    __syncthreads();
+    double s0 = 0.0, s1 = 0.0;
+    for (int w = 0; w < kCgBatchWaves; ++w) {
+        s0 += red[0][w];
+        s1 += red[1][w];
+    }
+    a = s0;
+    b = s1;
+}
+
+// Row pass over subgraph rows with v = Y (RHS: b_i and r_i = b_i - (L^w Y)_i,
+// written to r and p; FP64 |b|^2 and |r|^2 per coordinate) or v = p (APPLY:
+// Ap_i; FP64 p . Ap).  d0..d3 hold this lane's share of the dot products.
+template <int MODE>
+__device__ __forceinline__ void cg_batch_rows(const float* __restrict__ delta, int32_t k, const float2* v,
+                                             float2* ra, float2* rb, double& d0, double& d1, double& d2,
+                                             double& d3) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    for (int i = wave; i < k; i += kCgBatchWaves) {
+        const float2 xi = v[i];
+        const float* __restrict__ drow = delta + (int64_t)i * k;
+        float lx = 0.f, ly = 0.f, bx = 0.f, by = 0.f;
+        for (int j = lane; j < k; j += kWave) {
+            const float Dv = drow[j];
+            const float2 xj = v[j];
+            const float inv = j != i ? __builtin_amdgcn_rcpf(Dv) : 0.f;
+            const float w = inv * inv;
+            const float dx = xi.x - xj.x;
+            const float dy = xi.y - xj.y;
+            lx = fmaf(w, dx, lx);
+            ly = fmaf(w, dy, ly);
+            if (MODE == kCgRhs) {
+                const float rs = __builtin_amdgcn_rsqf(fmaf(dx, dx, fmaf(dy, dy, kMinSq)));
+                const float c = inv * rs;
+                bx = fmaf(c, dx, bx);
+                by = fmaf(c, dy, by);
+            }
+        }
+        const float sx = wave_sum(lx);
+        const float sy = wave_sum(ly);
+        if (MODE == kCgRhs) {
+            const float tx = wave_sum(bx);
+            const float ty = wave_sum(by);
+            const float2 rv = make_float2(tx - sx, ty - sy);
+            if (lane == 0) {
+                ra[i] = rv;
+                rb[i] = rv;
+                d0 += (double)tx * tx;
+                d1 += (double)ty * ty;
+                d2 += (double)rv.x * rv.x;
+                d3 += (double)rv.y * rv.y;
+            }
+        } else if (lane == 0) {
+            ra[i] = make_float2(sx, sy);
+            d0 += (double)xi.x * sx;
+            d1 += (double)xi.y * sy;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kCgBatchThreads) void cg_batch_kernel(const int64_t* __restrict__ node_off,
+                                                                   const int64_t* __restrict__ mat_off,
+                                                                   const float* __restrict__ delta_pool,
+                                                                   const float2* __restrict__ x_in,
+                                                                   float2* __restrict__ x_out, double tol2,
+                                                                   int32_t max_iter, int32_t* __restrict__ iters_out,
+                                                                   int32_t* __restrict__ conv_out) {
+    __shared__ float2 Y[kCgBatchMaxN], X[kCgBatchMaxN], Rv[kCgBatchMaxN], P[kCgBatchMaxN], AP[kCgBatchMaxN];
+    __shared__ double red[2][kCgBatchWaves];
+    const int g = blockIdx.x;
+    const int64_t base = node_off[g];
+    const int64_t kk = node_off[g + 1] - base;
+    if (kk < 1 || kk > kCgBatchMaxN) {  // uniform in the block
+        if (threadIdx.x == 0) {
+            if (iters_out) iters_out[g] = -1;
+            if (conv_out) conv_out[g] = 0;
+        }
+        return;
+    }
+    const int k = (int)kk;
+    const float* __restrict__ delta = delta_pool + mat_off[g];
+    // centred start x0 = Y - mean(Y), mean in FP64
+    double mx = 0.0, my = 0.0;
+    for (int i = threadIdx.x; i < k; i += kCgBatchThreads) {
+        const float2 y = x_in[base + i];
+        Y[i] = y;
+        mx += (double)y.x;
+        my += (double)y.y;
+    }
+    cg_batch_sum2(mx, my, red);
+    mx /= k;
+    my /= k;
+    for (int i = threadIdx.x; i < k; i += kCgBatchThreads)
+        X[i] = make_float2((float)((double)Y[i].x - mx), (float)((double)Y[i].y - my));
+    __syncthreads();
+    double b0 = 0.0, b1 = 0.0, r0 = 0.0, r1 = 0.0;
+    cg_batch_rows<kCgRhs>(delta, k, Y, Rv, P, b0, b1, r0, r1);
+    cg_batch_sum2(b0, b1, red);
+    cg_batch_sum2(r0, r1, red);
+    bool done = r0 <= tol2 * b0 && r1 <= tol2 * b1;
+    int it = 0;
+    for (; !done && it < max_iter; ++it) {
+        double p0 = 0.0, p1 = 0.0, unused0 = 0.0, unused1 = 0.0;
+        cg_batch_rows<kCgApply>(delta, k, P, AP, nullptr, p0, p1, unused0, unused1);
+        cg_batch_sum2(p0, p1, red);  // its barriers also order the Ap writes before the reads below
+        const float a0 = p0 > 0.0 ? (float)(r0 / p0) : 0.f;
+        const float a1 = p1 > 0.0 ? (float)(r1 / p1) : 0.f;
+        double n0 = 0.0, n1 = 0.0;
+        for (int i = threadIdx.x; i < k; i += kCgBatchThreads) {
+            const float2 pv = P[i], av = AP[i];
+            float2 xv = X[i], rv = Rv[i];
+            xv.x = fmaf(a0, pv.x, xv.x);
+            xv.y = fmaf(a1, pv.y, xv.y);
+            rv.x = fmaf(-a0, av.x, rv.x);
+            rv.y = fmaf(-a1, av.y, rv.y);
+            X[i] = xv;
+            Rv[i] = rv;
+            n0 += (double)rv.x * rv.x;
+            n1 += (double)rv.y * rv.y;
+        }
+        cg_batch_sum2(n0, n1, red);
+        const float e0 = r0 > 0.0 ? (float)(n0 / r0) : 0.f;
+        const float e1 = r1 > 0.0 ? (float)(n1 / r1) : 0.f;
+        for (int i = threadIdx.x; i < k; i += kCgBatchThreads) {
+            const float2 rv = Rv[i];
+            float2 pv = P[i];
+            pv.x = fmaf(e0, pv.x, rv.x);
+            pv.y = fmaf(e1, pv.y, rv.y);
+            P[i] = pv;
+        }
+        __syncthreads();  // p complete before the next apply
+        r0 = n0;
+        r1 = n1;
+        done = n0 <= tol2 * b0 && n1 <= tol2 * b1;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += kCgBatchThreads) x_out[base + i] = X[i];
+    if (threadIdx.x == 0) {
+        if (iters_out) iters_out[g] = it;
+        if (conv_out) conv_out[g] = done ? 1 : 0;
+    }
+}
+
 }  // namespace
 
 }  // namespace pprviz
@@ -366,6 +533,23 @@ ppr_status layout_step_exact(const float* delta, int32_t k, const float* x_in, f
     }
     if (cg_iters_out) *cg_iters_out = hs.iters;
     return hs.done ? PPR_OK : PPR_ENOCONV;
+}
+
+
+ppr_status pprviz_batch_step_exact(const ppr_batch* b, const float* delta_pool, const float* x_in, float* x_out,
+                                   double cg_tol, int32_t cg_max_iter, int32_t* iters_out, int32_t* converged_out,
+                                   void* stream) {
+    if (b == nullptr || b->n_graphs < 1 || b->n_nodes < 1 || !b->node_off || !b->mat_off) return PPR_EINVAL;
+    if (!delta_pool || !x_in || !x_out || x_in == x_out) return PPR_EINVAL;
+    if (!(cg_tol >= 0.0) || !std::isfinite(cg_tol) || cg_max_iter < 0) return PPR_EINVAL;
+    if (b->max_n < 1) return PPR_EINVAL;
+    if (b->max_n > kCgBatchMaxN) return PPR_EUNSUPPORTED;
+    if (pending_error() != PPR_OK) return PPR_EHIP;
+    hipLaunchKernelGGL(cg_batch_kernel, dim3((unsigned)b->n_graphs), dim3(kCgBatchThreads), 0,
+                       static_cast<hipStream_t>(stream), b->node_off, b->mat_off, delta_pool,
+                       reinterpret_cast<const float2*>(x_in), reinterpret_cast<float2*>(x_out), cg_tol * cg_tol,
+                       cg_max_iter, iters_out, converged_out);
+    return launch_status();
 }
 
 }  // extern "C"

@@ -335,6 +335,23 @@ def batch_max_n():
     return int(L.lib().pprviz_batch_max_n())
 
 
+def batch_step_exact(batch: "Batch", delta_pool, x, cg_tol=1e-6, cg_max_iter=1000, out=None):
+    """The exact (Guttman) step of every subgraph of a batch, one block per
+    subgraph.  ``delta_pool`` is the PDist pool pprviz_batch writes, ``x``
+    the positions [n_nodes, 2].  Returns (x_out, iterations [n_graphs],
+    converged [n_graphs]) as device int32 tensors."""
+    dev = batch.device
+    x = x.contiguous()
+    out = torch.empty_like(x) if out is None else out
+    iters = torch.empty(batch.n_graphs, dtype=torch.int32, device=dev)
+    conv = torch.empty(batch.n_graphs, dtype=torch.int32, device=dev)
+    cb = batch.c()
+    L.check("pprviz_batch_step_exact",
+            L.lib().pprviz_batch_step_exact(C.byref(cb), _ptr(delta_pool), _ptr(x), _ptr(out), cg_tol,
+                                            cg_max_iter, _ptr(iters), _ptr(conv), _stream(dev)))
+    return out, iters, conv
+
+
 def pprviz_batch(b: Batch, bufs, alpha=0.15, tol=1e-6, max_iter=100000, stress_iters=200):
     cb = b.c()
     st = L.lib().pprviz_batch(C.byref(cb), alpha, tol, max_iter, stress_iters, _ptr(bufs["x0"]), _ptr(bufs["x_out"]),

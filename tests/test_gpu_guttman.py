@@ -128,3 +128,85 @@ def test_exact_step_tiny_layouts(ops, k):
     want = O.majorization_step(Y.astype(np.float64), D.astype(np.float64))
     got = x.double().cpu().numpy()
     assert np.abs(got - want).max() <= 1e-4 * max(_scale(want), 1e-30) + 1e-7
+
+
+# ------------------------------------------- batch form (one block per subgraph)
+
+
+def _batch_case(ops, sizes, seed):
+    """A batch of edgeless subgraphs of the given sizes (the exact step reads
+    only node_off and mat_off), random distance matrices in the PDist pool
+    and uniform random starts."""
+    gb = synth.concat_graphs([synth.build_graph(int(n), [], []) for n in sizes])
+    Ds = [synth.random_distance_matrix(max(int(n), 2), seed + i)[:n, :n].copy() for i, n in enumerate(sizes)]
+    Ys = [synth.uniform_layout(int(n), seed + 500 + i) for i, n in enumerate(sizes)]
+    batch = ops.Batch(gb)
+    pool = _t(np.concatenate([D.ravel() for D in Ds]))
+    x = _t(np.concatenate(Ys))
+    return gb, batch, Ds, Ys, pool, x
+
+
+def test_batch_exact_step_matches_pseudo_inverse(ops):
+    # ragged sizes: 1 (the origin), 2, 3, a wave minus/plus one, several waves
+    sizes = [1, 2, 3, 5, 63, 64, 65, 97, 300, 513]
+    gb, batch, Ds, Ys, pool, x = _batch_case(ops, sizes, synth.BASE_SEED + 200)
+    print(f"[guttman batch] sizes={sizes}", flush=True)
+    out, iters, conv = ops.batch_step_exact(batch, pool, x, cg_tol=CG_TOL)
+    got = out.double().cpu().numpy()
+    iters = iters.cpu().numpy()
+    assert np.all(conv.cpu().numpy() == 1)
+    for g, n in enumerate(sizes):
+        a, b = int(gb.node_off[g]), int(gb.node_off[g + 1])
+        want = O.majorization_step(Ys[g].astype(np.float64), Ds[g].astype(np.float64))
+        err = np.abs(got[a:b] - want).max()
+        assert err <= 1e-4 * max(_scale(want), 1e-30) + 1e-7, (n, err, iters[g])
+        assert 0 <= iters[g] < 1000
+
+
+def test_batch_exact_step_at_the_largest_size_agrees_with_the_single_step(ops):
+    # the largest subgraph (all five CG vectors in 92 KB of LDS) beside two
+    # others; each subgraph against layout_step_exact on its own, and the
+    # 2304-node one against its defining equation L^w X+ = L^Y(Y) Y in FP64
+    sizes = [ops.batch_max_n(), 1000, 7]
+    assert sizes[0] == 2304
+    gb, batch, Ds, Ys, pool, x = _batch_case(ops, sizes, synth.BASE_SEED + 300)
+    print(f"[guttman batch] sizes={sizes}", flush=True)
+    out, iters, conv = ops.batch_step_exact(batch, pool, x, cg_tol=1e-6)
+    got = out.double().cpu().numpy()
+    assert np.all(conv.cpu().numpy() == 1)
+    for g, n in enumerate(sizes):
+        a, b = int(gb.node_off[g]), int(gb.node_off[g + 1])
+        single, it1 = ops.layout_step_exact(_t(Ds[g]), _t(Ys[g]), cg_tol=1e-6)
+        s = single.double().cpu().numpy()
+        assert np.abs(got[a:b] - s).max() <= 1e-5 * _scale(s), n
+        assert abs(int(iters[g]) - it1) <= 1, (n, int(iters[g]), it1)
+    n = sizes[0]
+    X = got[:n]
+    D64 = Ds[0].astype(np.float64)
+    Y64 = Ys[0].astype(np.float64)
+    rhs = O.laplacian_y(D64, Y64) @ Y64
+    res = O.laplacian_w(D64) @ X - rhs
+    assert np.linalg.norm(res[:, 0]) <= 2e-5 * np.linalg.norm(rhs[:, 0])
+    assert np.linalg.norm(res[:, 1]) <= 2e-5 * np.linalg.norm(rhs[:, 1])
+
+
+def test_batch_exact_step_cap_and_invalid_arguments(ops):
+    from paper_2112_14944_amd import _lib
+    sizes = [40, 200]
+    gb, batch, Ds, Ys, pool, x = _batch_case(ops, sizes, synth.BASE_SEED + 400)
+    out, iters, conv = ops.batch_step_exact(batch, pool, x, cg_tol=0.0, cg_max_iter=2)
+    assert np.all(iters.cpu().numpy() == 2) and np.all(conv.cpu().numpy() == 0)
+    assert torch.isfinite(out).all()
+    # two iterations from the same start match layout_step_exact's two
+    for g in range(2):
+        a, b = int(gb.node_off[g]), int(gb.node_off[g + 1])
+        s, _ = ops.layout_step_exact(_t(Ds[g]), _t(Ys[g]), cg_tol=0.0, cg_max_iter=2, allow_noconv=True)
+        sv = s.double().cpu().numpy()
+        assert np.abs(out.double().cpu().numpy()[a:b] - sv).max() <= 1e-5 * _scale(sv)
+    for kwargs in (dict(cg_tol=-1.0), dict(cg_tol=float("inf")), dict(cg_max_iter=-1)):
+        with pytest.raises(_lib.PprvizError) as ei:
+            ops.batch_step_exact(batch, pool, x, **kwargs)
+        assert ei.value.status == _lib.PPR_EINVAL
+    with pytest.raises(_lib.PprvizError) as ei:
+        ops.batch_step_exact(batch, pool, x, out=x)
+    assert ei.value.status == _lib.PPR_EINVAL
