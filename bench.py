@@ -240,6 +240,38 @@ def layout_metrics_leg(ops, dev, x, g, src, reps=3):
                 kernel="nd_kernel", pairs=k * (k - 1) // 2)
 
 
+def batch_exact_leg(ops, b, bufs, sizes, reps=3):
+    """The exact stress-majorization step for every subgraph of the batch in
+    one launch (pprviz_batch_step_exact, one block per subgraph), from the
+    batch's layout after its Jacobi sweeps, with the batch's PDist pool, CG to
+    1e-6.  Algorithmic bytes: 4 n_g^2 per pass over Delta_g (the right-hand
+    side, then one L^w apply per CG iteration of that subgraph)."""
+    import torch
+
+    best = None
+    iters = conv = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, iters, conv = ops.batch_step_exact(b, bufs["delta"], bufs["x_out"], cg_tol=1e-6)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+    it = iters.cpu().numpy().astype(np.int64)
+    nbytes = float((4 * sizes.astype(np.float64) ** 2 * (it + 1)).sum())
+    achieved = nbytes / (best * 1e-3) / 1e9
+    return dict(workload=f"exact majorization step of all {b.n_graphs} subgraphs of the batch (sizes 32..2048) "
+                         f"from their layouts after the Jacobi sweeps, CG to 1e-6, one launch",
+                kernel="cg_batch_kernel", ms=best, subgraphs_per_s=b.n_graphs / (best * 1e-3),
+                cg_iters_mean=float(it.mean()), cg_iters_max=int(it.max()),
+                converged=int(conv.cpu().numpy().sum()), bound="hbm", unit="GB/s", achieved=achieved,
+                peak=PEAK_HBM_GBS, frac=achieved / PEAK_HBM_GBS,
+                work=f"{nbytes:.3e} B: the right-hand side and one L^w apply per CG iteration, per subgraph")
+
+
 def layout_exact_leg(ops, dev, delta, sweeps=200, reps=3, cpu=False):
     """The exact stress-majorization step (layout_step_exact, conjugate
     gradients on L^w X = L^Y(Y) Y) on the 4096-node layout of the 10^6-node
@@ -543,6 +575,11 @@ def main():
             f"layout {stages['layout']['achieved']:.0f} GB/s, {stages['layout']['tflops']:.1f} TFLOP/s FP32 "
             f"({100 * stages['layout']['flop_frac']:.0f}% of the vector peak)")
 
+    batch_exact = batch_exact_leg(ops, b, bufs, sizes)
+    log(f"batched exact step ({G} subgraphs): {batch_exact['ms']:.2f} ms, CG iterations mean "
+        f"{batch_exact['cg_iters_mean']:.1f} max {batch_exact['cg_iters_max']}, {batch_exact['converged']} converged, "
+        f"{batch_exact['achieved']:.0f} GB/s algorithmic")
+
     # ---- plain path: one subgraph at a time through the C ABI
     plain = None
     if not args.no_plain:
@@ -676,6 +713,7 @@ def main():
         "level_dppr_gbp": gbp,
         "tau_push": tau,
         "layout_exact": exact,
+        "layout_exact_batch": batch_exact,
         "layout_metrics": metrics,
         "cpu_baseline": cpu,
     }

@@ -352,9 +352,7 @@ __device__ __forceinline__ void cg_batch_rows(const float* __restrict__ delta, i
         const float2 xi = v[i];
         const float* __restrict__ drow = delta + (int64_t)i * k;
         float lx = 0.f, ly = 0.f, bx = 0.f, by = 0.f;
-        for (int j = lane; j < k; j += kWave) {
-            const float Dv = drow[j];
-            const float2 xj = v[j];
+        auto pair = [&](int j, float Dv, float2 xj) {
             const float inv = j != i ? __builtin_amdgcn_rcpf(Dv) : 0.f;
             const float w = inv * inv;
             const float dx = xi.x - xj.x;
@@ -367,7 +365,22 @@ __device__ __forceinline__ void cg_batch_rows(const float* __restrict__ delta, i
                 bx = fmaf(c, dx, bx);
                 by = fmaf(c, dy, by);
             }
+        };
+        // 8 row segments in flight per wave; the terms are still added in
+        // ascending j per lane
+        int j = lane;
+        for (; j + 7 * kWave < k; j += 8 * kWave) {
+            float dv[8];
+            float2 xv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                dv[u] = drow[j + u * kWave];
+                xv[u] = v[j + u * kWave];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) pair(j + u * kWave, dv[u], xv[u]);
         }
+        for (; j < k; j += kWave) pair(j, drow[j], v[j]);
         const float sx = wave_sum(lx);
         const float sy = wave_sum(ly);
         if (MODE == kCgRhs) {
