@@ -210,3 +210,27 @@ def test_batch_exact_step_cap_and_invalid_arguments(ops):
     with pytest.raises(_lib.PprvizError) as ei:
         ops.batch_step_exact(batch, pool, x, out=x)
     assert ei.value.status == _lib.PPR_EINVAL
+
+
+def test_batch_exact_step_on_the_batch_pipeline_output(ops):
+    # 40 SBM subgraphs (sizes log-uniform in [32, 400]) through pprviz_batch
+    # (all-pairs PPR, PDist, 20 Jacobi sweeps), then the exact step of every
+    # subgraph from the sweeps' layout with the batch's own PDist pool: each
+    # against the FP64 pseudo-inverse step on the same inputs, and the stress
+    # of each subgraph does not rise (majorization)
+    graphs = synth.sbm_batch(40, 32, 400, seed=synth.BASE_SEED + 600)
+    gb = synth.concat_graphs(graphs)
+    batch = ops.Batch(gb)
+    x0 = torch.as_tensor(synth.uniform_layout(batch.n_nodes, synth.BASE_SEED + 601), device="cuda")
+    bufs = ops.pprviz_batch(batch, batch.buffers(x0), stress_iters=20)
+    print(f"[guttman batch] pipeline: {len(graphs)} subgraphs, {batch.n_nodes} nodes", flush=True)
+    out, iters, conv = ops.batch_step_exact(batch, bufs["delta"], bufs["x_out"], cg_tol=CG_TOL)
+    assert np.all(conv.cpu().numpy() == 1)
+    xs = bufs["x_out"].double().cpu().numpy()
+    got = out.double().cpu().numpy()
+    for g in range(len(graphs)):
+        a, b = int(gb.node_off[g]), int(gb.node_off[g + 1])
+        D = ops.graph_block(gb, bufs["delta"], g).double().cpu().numpy()
+        want = O.majorization_step(xs[a:b], D)
+        assert np.abs(got[a:b] - want).max() <= 1e-4 * _scale(want), g
+        assert O.stress(got[a:b], D) <= O.stress(xs[a:b], D) * (1 + 1e-6), g
