@@ -348,57 +348,72 @@ __device__ __forceinline__ void cg_batch_rows(const float* __restrict__ delta, i
                                              double& d3) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    for (int i = wave; i < k; i += kCgBatchWaves) {
-        const float2 xi = v[i];
-        const float* __restrict__ drow = delta + (int64_t)i * k;
-        float lx = 0.f, ly = 0.f, bx = 0.f, by = 0.f;
-        auto pair = [&](int j, float Dv, float2 xj) {
+    // two rows per wave at a time (i and i + 16), sharing each column's
+    // position load; 2 x 8 row segments of Delta in flight per wave
+    for (int i0 = wave; i0 < k; i0 += 2 * kCgBatchWaves) {
+        const int i1 = i0 + kCgBatchWaves;
+        const bool has1 = i1 < k;  // uniform in the wave
+        const float2 xi[2] = {v[i0], has1 ? v[i1] : make_float2(0.f, 0.f)};
+        const float* __restrict__ drow[2] = {delta + (int64_t)i0 * k, delta + (int64_t)(has1 ? i1 : i0) * k};
+        float lx[2] = {0.f, 0.f}, ly[2] = {0.f, 0.f}, bx[2] = {0.f, 0.f}, by[2] = {0.f, 0.f};
+        auto pair = [&](int r, int i, int j, float Dv, float2 xj) {
             const float inv = j != i ? __builtin_amdgcn_rcpf(Dv) : 0.f;
             const float w = inv * inv;
-            const float dx = xi.x - xj.x;
-            const float dy = xi.y - xj.y;
-            lx = fmaf(w, dx, lx);
-            ly = fmaf(w, dy, ly);
+            const float dx = xi[r].x - xj.x;
+            const float dy = xi[r].y - xj.y;
+            lx[r] = fmaf(w, dx, lx[r]);
+            ly[r] = fmaf(w, dy, ly[r]);
             if (MODE == kCgRhs) {
                 const float rs = __builtin_amdgcn_rsqf(fmaf(dx, dx, fmaf(dy, dy, kMinSq)));
                 const float c = inv * rs;
-                bx = fmaf(c, dx, bx);
-                by = fmaf(c, dy, by);
+                bx[r] = fmaf(c, dx, bx[r]);
+                by[r] = fmaf(c, dy, by[r]);
             }
         };
-        // 8 row segments in flight per wave; the terms are still added in
-        // ascending j per lane
         int j = lane;
         for (; j + 7 * kWave < k; j += 8 * kWave) {
-            float dv[8];
+            float dv[2][8];
             float2 xv[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                dv[u] = drow[j + u * kWave];
+                dv[0][u] = drow[0][j + u * kWave];
+                dv[1][u] = drow[1][j + u * kWave];
                 xv[u] = v[j + u * kWave];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) pair(j + u * kWave, dv[u], xv[u]);
-        }
-        for (; j < k; j += kWave) pair(j, drow[j], v[j]);
-        const float sx = wave_sum(lx);
-        const float sy = wave_sum(ly);
-        if (MODE == kCgRhs) {
-            const float tx = wave_sum(bx);
-            const float ty = wave_sum(by);
-            const float2 rv = make_float2(tx - sx, ty - sy);
-            if (lane == 0) {
-                ra[i] = rv;
-                rb[i] = rv;
-                d0 += (double)tx * tx;
-                d1 += (double)ty * ty;
-                d2 += (double)rv.x * rv.x;
-                d3 += (double)rv.y * rv.y;
+            for (int u = 0; u < 8; ++u) {
+                pair(0, i0, j + u * kWave, dv[0][u], xv[u]);
+                pair(1, i1, j + u * kWave, dv[1][u], xv[u]);
             }
-        } else if (lane == 0) {
-            ra[i] = make_float2(sx, sy);
-            d0 += (double)xi.x * sx;
-            d1 += (double)xi.y * sy;
+        }
+        for (; j < k; j += kWave) {
+            const float2 xj = v[j];
+            pair(0, i0, j, drow[0][j], xj);
+            pair(1, i1, j, drow[1][j], xj);
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            if (r == 1 && !has1) break;
+            const int i = r == 0 ? i0 : i1;
+            const float sx = wave_sum(lx[r]);
+            const float sy = wave_sum(ly[r]);
+            if (MODE == kCgRhs) {
+                const float tx = wave_sum(bx[r]);
+                const float ty = wave_sum(by[r]);
+                const float2 rv = make_float2(tx - sx, ty - sy);
+                if (lane == 0) {
+                    ra[i] = rv;
+                    rb[i] = rv;
+                    d0 += (double)tx * tx;
+                    d1 += (double)ty * ty;
+                    d2 += (double)rv.x * rv.x;
+                    d3 += (double)rv.y * rv.y;
+                }
+            } else if (lane == 0) {
+                ra[i] = make_float2(sx, sy);
+                d0 += (double)xi[r].x * sx;
+                d1 += (double)xi[r].y * sy;
+            }
         }
     }
 }
