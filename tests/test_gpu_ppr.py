@@ -200,9 +200,10 @@ def test_nonfinite_weights_reported(ops):
 
 def test_chung_lu_20000_all_pairs_sampled(ops):
     # Chung-Lu n=20000, gamma 2.5, mean degree 20, all 20000 sources to L1
-    # residual 1e-7 (T = 100): full FP32 n x n output; the oracle checks 40
-    # sampled sources, their PDist block, and one Jacobi step of 40 sampled
-    # rows of the full-size layout.
+    # residual 1e-7 (T = 100): full FP32 n x n output; the oracle checks 48
+    # sources (the 8 of highest degree, where pi_d(s, s) >= alpha d(s) is
+    # largest, and 40 seeded others), their PDist block, and one Jacobi step
+    # of those 48 rows of the full-size layout.
     g = synth.chung_lu(20000, 2.5, 20, synth.BASE_SEED + 2)
     n = g.n
     print(f"[chung-lu n=20000] n={n} nnz={g.nnz}", flush=True)
@@ -210,7 +211,11 @@ def test_chung_lu_20000_all_pairs_sampled(ops):
     ppr, dppr, T, resid = ops.ppr_matrix(csr, np.arange(n), tol=1e-7, check_residual=True)
     assert T == 100
     assert np.abs(resid - (1 - ALPHA) ** 100).max() <= 2e-6
-    sample = synth.random_sources(g, 40, 31)
+    deg = np.diff(g.row_ptr)
+    hubs = np.argsort(-deg, kind="stable")[:8]
+    rnd = synth.random_sources(g, 48, 31)
+    sample = np.concatenate([hubs, rnd[~np.isin(rnd, hubs)][:40]]).astype(np.int32)
+    assert len(sample) == 48 and deg[sample[:8]].min() >= deg.max() // 2
     est, dppr_o, _, _, d = oracle_ppr(g, sample, tol=1e-7)
     sidx = torch.as_tensor(sample, device="cuda").long()
     assert_ppr_close(ppr[sidx], dppr[sidx], est, dppr_o, d[sample])
