@@ -117,6 +117,32 @@ ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src,
                       double* resid_out, int32_t* iters_out,
                       void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * ppr_matrix for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation, kernels and results as ppr_matrix, with the workspace
+ * taken from a fixed scratch array inside the library instead of a caller
+ * buffer.  Inputs and outputs are still the caller's.  The call allocates
+ * nothing (no hipMalloc/hipFree, no allocating library routine).
+ *
+ * Limit: the workspace ppr_matrix_workspace(g, n_src, n_tgt) would ask for
+ * must fit ppr_matrix_noalloc_max_scratch() bytes (8 MiB), else the call
+ * returns PPR_EUNSUPPORTED before any launch.  That covers, for example, the
+ * LDS-resident path (n <= 2304) up to about 1.9 million arcs unweighted.
+ *
+ * The scratch is one array per GPU, held from the first call on that GPU
+ * until the process ends (its device address is looked up once per device).
+ * Every call on one GPU uses the same array and leaves it holding that call's
+ * intermediates: calls that overlap on one GPU (on different streams, or
+ * from different host threads without ordering) race and give undefined
+ * results.  Calls on one stream are ordered and safe.
+ */
+size_t ppr_matrix_noalloc_max_scratch(void);
+ppr_status ppr_matrix_noalloc(const ppr_csr* g, const int32_t* src, int32_t n_src,
+                              const int32_t* tgt, int32_t n_tgt, float alpha, double tol_l1,
+                              int32_t max_iter, float* ppr_out, float* dppr_out,
+                              double* resid_out, int32_t* iters_out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Level-l DPPR by Group Forward-Push (Section 3.2 Definition def:spprdeg;
  * Section 4.2 Algorithm alg:fwdpushsn, Eq. eq:rmax)

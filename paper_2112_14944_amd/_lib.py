@@ -42,6 +42,9 @@ _SIGS = {
     "ppr_matrix_workspace": (sz, [C.POINTER(ppr_csr), i32, i32]),
     "ppr_matrix": (C.c_int, [C.POINTER(ppr_csr), vp, i32, vp, i32, f32, f64, i32, vp, vp,
                              C.POINTER(f64), C.POINTER(i32), vp, sz, vp]),
+    "ppr_matrix_noalloc_max_scratch": (sz, []),
+    "ppr_matrix_noalloc": (C.c_int, [C.POINTER(ppr_csr), vp, i32, vp, i32, f32, f64, i32, vp, vp,
+                                     C.POINTER(f64), C.POINTER(i32), vp]),
     "gfp_workspace": (sz, [C.POINTER(ppr_csr), i32, i32]),
     "gfp_level_dppr": (C.c_int, [C.POINTER(ppr_csr), vp, vp, i32, i64, f32, f64, i32, vp, vp, vp,
                                  C.POINTER(i32), vp, sz, vp]),

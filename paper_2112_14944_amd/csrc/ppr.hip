@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "ppr_core.hpp"
 #include "internal.hpp"
@@ -246,6 +247,81 @@ void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int3
     }
 }
 
+
+// Scratch memory of ppr_matrix_noalloc: a fixed device array, one copy per
+// GPU, that replaces the caller's workspace for callers that cannot allocate
+// (graph capture, tight serving loops).  Host code never passes the array's
+// name to a kernel: scratch_address resolves it once per device, with that
+// device current, and keeps the device address.
+constexpr size_t kScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+
+static ppr_status scratch_address(hipStream_t s, void** out) {
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    if (s != nullptr) {
+        hipDevice_t d = 0;
+        PPRVIZ_HIP_TRY(hipStreamGetDevice(s, &d));
+        dev = (int)d;
+    } else {
+        PPRVIZ_HIP_TRY(hipGetDevice(&dev));
+    }
+    if (dev < 0 || dev >= kMaxDevices) return PPR_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[dev] == nullptr) {
+        int cur = 0;
+        PPRVIZ_HIP_TRY(hipGetDevice(&cur));
+        if (cur != dev) PPRVIZ_HIP_TRY(hipSetDevice(dev));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) PPRVIZ_HIP_TRY(hipSetDevice(cur));
+        if (e != hipSuccess || p == nullptr) return PPR_EHIP;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return PPR_OK;
+}
+
+// ppr_matrix with the workspace given (the caller's, or this GPU's scratch).
+static ppr_status ppr_matrix_impl(const ppr_csr* g, const int32_t* src, int32_t n_src, const int32_t* tgt,
+                                  int32_t n_tgt, float alpha, double tol_l1, int32_t max_iter, float* ppr_out,
+                                  float* dppr_out, double* resid_out, int32_t* iters_out, void* ws,
+                                  size_t ws_bytes, void* stream, bool scratch_ws) {
+    ppr_status st = validate_csr(g);
+    if (st != PPR_OK) return st;
+    if (n_src < 0 || n_tgt < 0 || (n_src > 0 && src == nullptr)) return PPR_EINVAL;
+    if (tgt == nullptr && n_tgt != g->n) return PPR_EINVAL;
+    if (!(alpha > 0.0f && alpha < 1.0f) || max_iter < 0) return PPR_EINVAL;
+    if ((int64_t)n_src * (int64_t)std::max(n_tgt, 1) > ((int64_t)1 << 40)) return PPR_EUNSUPPORTED;
+    if (g->n > kStreamMaxN) return PPR_EUNSUPPORTED;
+    int32_t T = 0, conv = 1;
+    st = pprviz_pushes_for_tolerance(alpha, tol_l1, max_iter, &T, &conv);
+    if (st != PPR_OK) return st;
+    if (iters_out) *iters_out = T;
+    if (n_src == 0) return conv ? PPR_OK : PPR_ENOCONV;
+    WsCursor cur{static_cast<char*>(ws), ws_bytes};
+    PprWs w;
+    ppr_ws_layout(cur, g->n, g->nnz, g->weight != nullptr, n_src, &w);
+    if (ws == nullptr || cur.used > ws_bytes) return scratch_ws ? PPR_EUNSUPPORTED : PPR_EWORKSPACE;
+    if (pending_error() != PPR_OK) return PPR_EHIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int n = g->n;
+    launch_degree(g->row_ptr, g->weight, n, w.deg, w.invd, s);
+
+    ppr_forward(g, src, n_src, tgt, n_tgt, alpha, T, ppr_out, dppr_out, w.deg, w.invd, w.resid, w, s);
+    st = launch_status();
+    if (st != PPR_OK) return st;
+    if (resid_out) {
+        PPRVIZ_HIP_TRY(hipMemcpyAsync(resid_out, w.resid, sizeof(double) * n_src, hipMemcpyDeviceToHost, s));
+        PPRVIZ_HIP_TRY(hipStreamSynchronize(s));
+        for (int i = 0; i < n_src; ++i)
+            if (!isfinite(resid_out[i])) return PPR_ENONFINITE;
+    }
+    return conv ? PPR_OK : PPR_ENOCONV;
+}
+
 }  // namespace pprviz
 
 using namespace pprviz;
@@ -309,37 +385,26 @@ ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src, const
                       int32_t n_tgt, float alpha, double tol_l1, int32_t max_iter, float* ppr_out,
                       float* dppr_out, double* resid_out, int32_t* iters_out, void* ws, size_t ws_bytes,
                       void* stream) {
+    return ppr_matrix_impl(g, src, n_src, tgt, n_tgt, alpha, tol_l1, max_iter, ppr_out, dppr_out, resid_out,
+                           iters_out, ws, ws_bytes, stream, false);
+}
+
+size_t ppr_matrix_noalloc_max_scratch(void) { return kScratchBytes; }
+
+ppr_status ppr_matrix_noalloc(const ppr_csr* g, const int32_t* src, int32_t n_src, const int32_t* tgt,
+                              int32_t n_tgt, float alpha, double tol_l1, int32_t max_iter, float* ppr_out,
+                              float* dppr_out, double* resid_out, int32_t* iters_out, void* stream) {
+    // The workspace bound is checked before the scratch address is looked up,
+    // so an oversized request fails without touching the device.
     ppr_status st = validate_csr(g);
     if (st != PPR_OK) return st;
-    if (n_src < 0 || n_tgt < 0 || (n_src > 0 && src == nullptr)) return PPR_EINVAL;
-    if (tgt == nullptr && n_tgt != g->n) return PPR_EINVAL;
-    if (!(alpha > 0.0f && alpha < 1.0f) || max_iter < 0) return PPR_EINVAL;
-    if ((int64_t)n_src * (int64_t)std::max(n_tgt, 1) > ((int64_t)1 << 40)) return PPR_EUNSUPPORTED;
-    if (g->n > kStreamMaxN) return PPR_EUNSUPPORTED;
-    int32_t T = 0, conv = 1;
-    st = pprviz_pushes_for_tolerance(alpha, tol_l1, max_iter, &T, &conv);
+    if (n_src < 0) return PPR_EINVAL;
+    if (ppr_matrix_workspace(g, n_src, n_tgt) > kScratchBytes) return PPR_EUNSUPPORTED;
+    void* scr = nullptr;
+    st = scratch_address(static_cast<hipStream_t>(stream), &scr);
     if (st != PPR_OK) return st;
-    if (iters_out) *iters_out = T;
-    if (n_src == 0) return conv ? PPR_OK : PPR_ENOCONV;
-    WsCursor cur{static_cast<char*>(ws), ws_bytes};
-    PprWs w;
-    ppr_ws_layout(cur, g->n, g->nnz, g->weight != nullptr, n_src, &w);
-    if (ws == nullptr || cur.used > ws_bytes) return PPR_EWORKSPACE;
-    if (pending_error() != PPR_OK) return PPR_EHIP;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int n = g->n;
-    launch_degree(g->row_ptr, g->weight, n, w.deg, w.invd, s);
-
-    ppr_forward(g, src, n_src, tgt, n_tgt, alpha, T, ppr_out, dppr_out, w.deg, w.invd, w.resid, w, s);
-    st = launch_status();
-    if (st != PPR_OK) return st;
-    if (resid_out) {
-        PPRVIZ_HIP_TRY(hipMemcpyAsync(resid_out, w.resid, sizeof(double) * n_src, hipMemcpyDeviceToHost, s));
-        PPRVIZ_HIP_TRY(hipStreamSynchronize(s));
-        for (int i = 0; i < n_src; ++i)
-            if (!isfinite(resid_out[i])) return PPR_ENONFINITE;
-    }
-    return conv ? PPR_OK : PPR_ENOCONV;
+    return ppr_matrix_impl(g, src, n_src, tgt, n_tgt, alpha, tol_l1, max_iter, ppr_out, dppr_out, resid_out,
+                           iters_out, scr, kScratchBytes, stream, true);
 }
 
 }  // extern "C"

@@ -93,6 +93,35 @@ def ppr_matrix(g: Csr, src, tgt=None, alpha=0.15, tol=1e-6, max_iter=100000, wan
     return ppr, dppr, iters.value, (resid[:n_src] if resid is not None else None)
 
 
+def ppr_matrix_noalloc(g: Csr, src, tgt=None, alpha=0.15, tol=1e-6, max_iter=100000, ppr=None, dppr=None,
+                       check_residual=False, allow_noconv=False):
+    """ppr_matrix through the entry point that allocates nothing: the library
+    takes its workspace from its own per-GPU scratch array.  ``ppr`` and
+    ``dppr`` are caller-owned [n_src, n_tgt] FP32 outputs (either may be
+    None).  Returns (pushes, resid)."""
+    dev = g.row_ptr.device
+    src = torch.as_tensor(src, dtype=torch.int32, device=dev).contiguous()
+    n_src = int(src.numel())
+    if tgt is not None:
+        tgt = torch.as_tensor(tgt, dtype=torch.int32, device=dev).contiguous()
+        n_tgt = int(tgt.numel())
+    else:
+        n_tgt = g.n
+    for o in (ppr, dppr):
+        if o is not None:
+            assert o.shape == (n_src, n_tgt) and o.dtype == torch.float32 and o.is_contiguous() and o.is_cuda
+    cg = g.c()
+    resid = np.zeros(max(n_src, 1), dtype=np.float64) if check_residual else None
+    iters = C.c_int32()
+    st = L.lib().ppr_matrix_noalloc(C.byref(cg), _ptr(src), n_src, _ptr(tgt), n_tgt, alpha, tol, max_iter,
+                                    _ptr(ppr), _ptr(dppr),
+                                    resid.ctypes.data_as(C.POINTER(C.c_double)) if resid is not None else None,
+                                    C.byref(iters), _stream(dev))
+    allow = (L.PPR_OK, L.PPR_ENOCONV) if allow_noconv else (L.PPR_OK,)
+    L.check("ppr_matrix_noalloc", st, allow)
+    return iters.value, (resid[:n_src] if resid is not None else None)
+
+
 def gfp_level_dppr(g: Csr, leaves, alpha=0.15, r_max=0.0, max_rounds=10000, want_est=False, want_resid=False,
                    allow_noconv=False):
     """Level-l DPPR between supernodes by Group Forward-Push in rounds.
