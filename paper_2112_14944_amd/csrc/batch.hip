@@ -28,6 +28,17 @@ namespace pprviz {
 constexpr int kBatchMaxN = Res<16>::NMAX;  // 2304
 constexpr int kPlanThreads = 1024;
 
+// One layout strip with everything its wave needs to start, so that a strip
+// costs one scalar load of its record (issued a strip ahead) before its 1/Delta
+// stream starts.
+struct __attribute__((aligned(16))) StripRec {
+    int32_t k;     // subgraph size
+    int32_t sj;    // S << 16 | J
+    int64_t node;  // first node of the subgraph (positions)
+    int64_t iv;    // offset of its 1/Delta block
+    int64_t pb;    // offset of its partial blocks
+};
+
 struct BatchPlan {
     int32_t* order;      // [G] subgraph ids, largest first
     int64_t* tile_pre;   // [G+1] prefix of PPR tiles in LPT order
@@ -35,8 +46,8 @@ struct BatchPlan {
     int64_t* rb_pre;     // [G+1] prefix of 16-row layout blocks (subgraph order)
     int32_t* pd_graph;   // subgraph of each PDist tile item
     int32_t* rb_graph;   // subgraph of each layout row-block item
-    int64_t* pt_pre;     // [G+1] prefix of 64x64 pair tiles (I <= J) of the layout sweeps
-    int32_t* pt_graph;   // subgraph of each pair tile
+    int64_t* pt_pre;     // [G+1] prefix of the layout sweeps' strips (256 rows x 64 columns)
+    StripRec* strip_tab; // [pt_pre[G]] layout strips, largest first
     int64_t* rt_pre;     // [G+1] prefix of 64-row tiles (sweep finalize items)
     int32_t* rt_graph;   // subgraph of each 64-row tile
     int64_t* pb_pre;     // [G+1] prefix of the partial blocks, T*T*64 floats per subgraph
@@ -92,11 +103,23 @@ __device__ __forceinline__ int64_t plan_count(int which, int n) {
         case 0: return tiles_of(n);                                          // PPR source tiles
         case 1: return T * T;                                                // PDist 64x64 tiles
         case 2: return (n + kLayoutRowsPerBlock - 1) / kLayoutRowsPerBlock;  // stress row blocks
-        case 3: return T * (T + 1) / 2;                                      // pair tiles I <= J
+        case 3: return strip_count(T);                                       // layout strips (S, J)
         case 4: return T;                                                    // 64-row tiles
         case 5: return T * T * kPT;                                          // partial-block floats
         default: return (int64_t)n * inv_ld(n);                              // 1/Delta pool floats
     }
+}
+
+// Size class of a strip for the largest-first order: its pair count (live
+// rows times columns, at most 256 x 64) in steps of 64, largest first.
+constexpr int kStripClasses = kStripBlocks * kPT * kPT / 64;
+
+__device__ __forceinline__ int strip_class(int k, int T, int S, int J) {
+    const int d = J - kStripBlocks * S;
+    const int nl = min(kStripBlocks, min(T - kStripBlocks * S, d + 1));
+    const int rows = min(nl * kPT, k - kStripBlocks * S * kPT);
+    const int cols = min(kPT, k - J * kPT);
+    return (kStripBlocks * kPT * kPT - rows * cols) / 64;
 }
 
 __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t* __restrict__ node_off, int32_t G,
@@ -158,8 +181,51 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t*
         for (int64_t i = p.rb_pre[g]; i < p.rb_pre[g + 1]; ++i) p.rb_graph[i] = g;
     }
     for (int g = tid; g < G; g += kPlanThreads) {
-        for (int64_t i = p.pt_pre[g]; i < p.pt_pre[g + 1]; ++i) p.pt_graph[i] = g;
         for (int64_t i = p.rt_pre[g]; i < p.rt_pre[g + 1]; ++i) p.rt_graph[i] = g;
+    }
+    // Layout strips of every subgraph, by size largest first (a counting sort
+    // over size classes of 64 pairs), so that the sweeps' static deal of
+    // strips to waves is even.  Which wave runs a strip never changes a sum:
+    // each strip writes its own partial slots.
+    __shared__ int32_t scls[kStripClasses];
+    for (int i = tid; i < kStripClasses; i += kPlanThreads) scls[i] = 0;
+    __syncthreads();
+    for (int g = tid; g < G; g += kPlanThreads) {
+        const int k = graph_n(node_off, g);
+        const int T = (k + kPT - 1) / kPT;
+        const int ns = (int)strip_count(T);
+        for (int t = 0; t < ns; ++t) {
+            int S, J;
+            strip_sj(t, T, S, J);
+            atomicAdd(&scls[strip_class(k, T, S, J)], 1);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int32_t run = 0;
+        for (int c = 0; c < kStripClasses; ++c) {
+            const int32_t n = scls[c];
+            scls[c] = run;
+            run += n;
+        }
+    }
+    __syncthreads();
+    for (int g = tid; g < G; g += kPlanThreads) {
+        const int k = graph_n(node_off, g);
+        const int T = (k + kPT - 1) / kPT;
+        const int ns = (int)strip_count(T);
+        for (int t = 0; t < ns; ++t) {
+            int S, J;
+            strip_sj(t, T, S, J);
+            const int pos = atomicAdd(&scls[strip_class(k, T, S, J)], 1);
+            StripRec r;
+            r.k = k;
+            r.sj = (S << 16) | J;
+            r.node = node_off[g];
+            r.iv = p.iv_pre[g];
+            r.pb = p.pb_pre[g];
+            p.strip_tab[pos] = r;
+        }
     }
     // Sizes are sorted descending, so each tile width owns a contiguous range
     // of positions: n > Res<32>::NMAX (16 columns), then n > Res<64>::NMAX
@@ -297,40 +363,40 @@ __global__ __launch_bounds__(256) void batch_layout_kernel(const int64_t* __rest
     }
 }
 
-// Pair-tile pass over every subgraph (see pair_tile): wave w of the grid
-// takes tiles w, w + W, w + 2W, ... (W waves in all); tiles cost about the
-// same, so the static deal is even.
-// At least 5 waves per SIMD (96 VGPRs): the chunk loads in flight need the
-// occupancy more than the scheduler needs the registers.
+// Strip pass over every subgraph (see strip): wave w of the grid takes
+// strips w, w + W, w + 2W, ... (W waves in all) of the plan's largest-first
+// strip table, a static deal.
 template <int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8)))
-void batch_pair_kernel(const int64_t* __restrict__ node_off,
-                                                         const int64_t* __restrict__ mat_off, int32_t G,
-                                                         const int64_t* __restrict__ pt_pre,
-                                                         const int32_t* __restrict__ pt_graph,
-                                                         const int64_t* __restrict__ pb_pre,
-                                                         const int64_t* __restrict__ iv_pre,
+__global__ __launch_bounds__(256) void batch_pair_kernel(const int64_t* __restrict__ pt_pre, int32_t G,
+                                                         const StripRec* __restrict__ strip_tab,
                                                          const float* __restrict__ inv,
                                                          const float2* __restrict__ x, float* __restrict__ px,
-                                                         float* __restrict__ py, float* __restrict__ pw) {
-    __shared__ PairLdsOf<MODE> lds[4];
+                                                         float* __restrict__ py) {
+    __shared__ StripLds<MODE> lds[4];
     const int wave = threadIdx.x >> 6;
     const int64_t total = pt_pre[G];
     const int64_t W = (int64_t)gridDim.x * 4;
-    for (int64_t item = (int64_t)blockIdx.x * 4 + wave; item < total; item += W) {
-        const int64_t it = __builtin_amdgcn_readfirstlane((int)item);
-        const int g = __builtin_amdgcn_readfirstlane(pt_graph[it]);
-        const int k = graph_n(node_off, g);
+    int64_t item = __builtin_amdgcn_readfirstlane((int)((int64_t)blockIdx.x * 4 + wave));
+    if (item >= total) return;
+    StripRec cur = strip_tab[item];
+    while (true) {
+        const int64_t next = item + W;
+        // the next record is loaded before this strip's work, so its latency
+        // overlaps the strip
+        StripRec nxt = cur;
+        if (next < total) nxt = strip_tab[next];
+        const int k = __builtin_amdgcn_readfirstlane(cur.k);
+        const int sj = __builtin_amdgcn_readfirstlane(cur.sj);
         const int T = (k + kPT - 1) / kPT;
-        int I, J;
-        pair_tile_ij((int)(it - pt_pre[g]), I, J);
-        const int64_t pb = pb_pre[g];
-        pair_tile<true, MODE>(inv + iv_pre[g], inv_ld(k), k, x + node_off[g], I, J, T, px + pb, py + pb, pw + pb,
-                              lds[wave]);
+        strip<MODE>(inv + cur.iv, inv_ld(k), k, x + cur.node, sj >> 16, sj & 0xffff, T, px + cur.pb, py + cur.pb,
+                    lds[wave]);
+        if (next >= total) break;
+        item = next;
+        cur = nxt;
     }
 }
 
-// Combine the partial blocks: one wave per 64-row tile of a subgraph.
+// Combine the partial blocks: one wave per 64-row block of a subgraph.
 template <int MODE>
 __global__ __launch_bounds__(256) void batch_pair_finalize_kernel(const int64_t* __restrict__ node_off, int32_t G,
                                                                   const int64_t* __restrict__ rt_pre,
@@ -338,7 +404,6 @@ __global__ __launch_bounds__(256) void batch_pair_finalize_kernel(const int64_t*
                                                                   const int64_t* __restrict__ pb_pre,
                                                                   const float* __restrict__ px,
                                                                   const float* __restrict__ py,
-                                                                  const float* __restrict__ pw,
                                                                   const float2* __restrict__ x,
                                                                   float2* __restrict__ xout,
                                                                   float* __restrict__ wsum) {
@@ -353,8 +418,7 @@ __global__ __launch_bounds__(256) void batch_pair_finalize_kernel(const int64_t*
         if (i >= k) continue;
         const int64_t nb = node_off[g];
         const int64_t pb = pb_pre[g];
-        pair_finalize<MODE>(i, T, px + pb, py + pb, pw + pb, x + nb, xout ? xout + nb : nullptr,
-                            wsum ? wsum + nb : nullptr);
+        strip_finalize<MODE>(i, T, px + pb, py + pb, x + nb, xout ? xout + nb : nullptr, wsum + nb);
     }
 }
 
@@ -383,9 +447,8 @@ struct BatchWs {
     float* wsum;  // per node sum_j Delta^-2
     float* xtmp;
     double* part;
-    float* px;  // pair-tile partial blocks of the sweeps (x, y, weight)
+    float* px;  // strip partial blocks of the sweeps (x, y; the weight pass uses px)
     float* py;
-    float* pw;
     BatchPlan plan;
 };
 
@@ -406,7 +469,6 @@ static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     const size_t pblk = (size_t)(b->pool_size / 4096 + b->n_nodes / 32 + b->n_graphs + 1) * kPT;
     t.px = c.template take<float>(pblk);
     t.py = c.template take<float>(pblk);
-    t.pw = c.template take<float>(pblk);
     t.plan.order = c.template take<int32_t>((size_t)b->n_graphs);
     t.plan.tile_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
     t.plan.pd_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
@@ -415,9 +477,10 @@ static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     // sum_g ceil(n_g/16) <= n_nodes/16 + G
     t.plan.pd_graph = c.template take<int32_t>((size_t)(b->pool_size / 4096 + b->n_nodes / 32 + b->n_graphs + 1));
     t.plan.rb_graph = c.template take<int32_t>((size_t)(b->n_nodes / kLayoutRowsPerBlock + b->n_graphs + 1));
-    // pair tiles: sum_g T(T+1)/2 <= pool/8192 + 3 n_nodes/128 + G; 64-row tiles <= n_nodes/64 + G
+    // strips: sum_g strip_count(T) <= sum_g T(T+1)/2 <= pool/8192 + 3 n_nodes/128 + G;
+    // 64-row tiles <= n_nodes/64 + G
     t.plan.pt_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
-    t.plan.pt_graph = c.template take<int32_t>((size_t)(b->pool_size / 8192 + 3 * b->n_nodes / 128 + b->n_graphs + 1));
+    t.plan.strip_tab = c.template take<StripRec>((size_t)(b->pool_size / 8192 + 3 * b->n_nodes / 128 + b->n_graphs + 1));
     t.plan.rt_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
     t.plan.rt_graph = c.template take<int32_t>((size_t)(b->n_nodes / kPT + b->n_graphs + 1));
     t.plan.pb_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
@@ -505,12 +568,10 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     const unsigned wgrid = (unsigned)cus * pair_blocks_per_cu<kPairW>();
     const unsigned fgrid = (unsigned)cus * 8;
     // per-node weight sums, from the pair tiles in the order the sweeps use
-    hipLaunchKernelGGL((batch_pair_kernel<kPairW>), dim3(wgrid), dim3(256), 0, s, b->node_off, b->mat_off, G,
-                       w.plan.pt_pre, w.plan.pt_graph, w.plan.pb_pre, w.plan.iv_pre, w.inv,
-                       reinterpret_cast<const float2*>(x0),
-                       w.px, w.py, w.pw);
+    hipLaunchKernelGGL((batch_pair_kernel<kPairW>), dim3(wgrid), dim3(256), 0, s, w.plan.pt_pre, G, w.plan.strip_tab,
+                       w.inv, reinterpret_cast<const float2*>(x0), w.px, w.py);
     hipLaunchKernelGGL((batch_pair_finalize_kernel<kPairW>), dim3(fgrid), dim3(256), 0, s, b->node_off, G,
-                       w.plan.rt_pre, w.plan.rt_graph, w.plan.pb_pre, w.px, w.py, w.pw,
+                       w.plan.rt_pre, w.plan.rt_graph, w.plan.pb_pre, w.px, w.py,
                        reinterpret_cast<const float2*>(x0), nullptr, w.wsum);
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[3], s));
 
@@ -524,11 +585,10 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     }
     for (int it = 0; it < stress_iters; ++it) {
         float2* out = bufs[next];
-        hipLaunchKernelGGL((batch_pair_kernel<kPairStep>), dim3(pgrid), dim3(256), 0, s, b->node_off, b->mat_off,
-                           G, w.plan.pt_pre, w.plan.pt_graph, w.plan.pb_pre, w.plan.iv_pre, w.inv, cur, w.px, w.py,
-                           w.pw);
+        hipLaunchKernelGGL((batch_pair_kernel<kPairStep>), dim3(pgrid), dim3(256), 0, s, w.plan.pt_pre, G,
+                           w.plan.strip_tab, w.inv, cur, w.px, w.py);
         hipLaunchKernelGGL((batch_pair_finalize_kernel<kPairStep>), dim3(fgrid), dim3(256), 0, s, b->node_off, G,
-                           w.plan.rt_pre, w.plan.rt_graph, w.plan.pb_pre, w.px, w.py, w.pw, cur, out, w.wsum);
+                           w.plan.rt_pre, w.plan.rt_graph, w.plan.pb_pre, w.px, w.py, cur, out, w.wsum);
         cur = out;
         next ^= 1;
     }
