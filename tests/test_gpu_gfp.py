@@ -17,7 +17,22 @@ from gpu_util import ALPHA, get_ops
 
 pytestmark = pytest.mark.gpu
 
-REL = 2e-5   # FP32 rounds against FP64, relative to the largest value
+# FP32 rounds against FP64, relative to the largest value.  Every push adds
+# nonnegative terms, so each round leaves each entry within about one unit
+# roundoff u = 2^-24 of its value on top of the error it carried in; after
+# T rounds the entries are within about T u.  The cases here run up to
+# T = 86 rounds: 2 T u = 1.0e-5 (the largest ratio measured on MI355X over
+# these tests is 4.7e-6).
+REL = 1e-5
+WORST = [0.0]
+
+
+def _within_rel(err, scale):
+    """err <= REL * scale; keeps the largest ratio err / scale seen."""
+    ratio = float(err) / max(float(scale), 1e-300)
+    WORST[0] = max(WORST[0], ratio)
+    print(f"[gfp rel] {ratio:.3e} (worst so far {WORST[0]:.3e})", flush=True)
+    assert ratio <= REL, ratio
 
 
 @pytest.fixture(scope="module")
@@ -72,10 +87,10 @@ def test_zero_threshold_is_the_truncated_series(ops, n, blocks, k_ragged, weight
         ppr, _, _ = O.ppr_power_iteration(P, np.arange(n), ALPHA, fixed_iters=T)
         want = O.level_dppr(ppr * d[:, None], leaves)
         got = out.double().cpu().numpy()
-        assert np.abs(got - want).max() <= REL * np.abs(want).max()
+        _within_rel(np.abs(got - want).max(), np.abs(want).max())
         e_o, R_o, ne_o, r_o, _ = O.group_forward_push_rounds(W, leaves, ALPHA, 0.0, T)
-        assert np.abs(est.double().cpu().numpy() - ne_o).max() <= REL * np.abs(ne_o).max()
-        assert np.abs(resid.double().cpu().numpy() - R_o).max() <= REL * max(np.abs(R_o).max(), 1e-30)
+        _within_rel(np.abs(est.double().cpu().numpy() - ne_o).max(), np.abs(ne_o).max())
+        _within_rel(np.abs(resid.double().cpu().numpy() - R_o).max(), max(np.abs(R_o).max(), 1e-30))
 
 
 @pytest.mark.parametrize("weighted", [False, True])
@@ -98,7 +113,7 @@ def test_threshold_result_is_valid(ops, weighted, r_max):
     assert np.abs(got - agg).max() <= 1e-6 * np.abs(agg).max()
     # invariant: estimate + error term = exact level-l DPPR
     err = O.gfp_error_term(pi_d, leaves, R, d)
-    assert np.abs(got + err - L).max() <= REL * np.abs(L).max()
+    _within_rel(np.abs(got + err - L).max(), np.abs(L).max())
     # error bound of Lemma lem:fpsn-correct (undirected: r_max * mean degree)
     bound = r_max * np.array([d[F].mean() for F in leaves])
     gap = L - got
@@ -130,9 +145,9 @@ def test_rows_gathered_by_a_whole_wave(ops, weighted):
         out, est, _, rounds, _ = ops.gfp_level_dppr(csr, leaves, ALPHA, 0.0, T, want_est=True, allow_noconv=True)
         ppr, _, _ = O.ppr_power_iteration(P, np.arange(g.n), ALPHA, fixed_iters=T)
         want = O.level_dppr(ppr * d[:, None], leaves)
-        assert np.abs(out.double().cpu().numpy() - want).max() <= REL * np.abs(want).max()
+        _within_rel(np.abs(out.double().cpu().numpy() - want).max(), np.abs(want).max())
         _, _, ne_o, _, _ = O.group_forward_push_rounds(W, leaves, ALPHA, 0.0, T)
-        assert np.abs(est.double().cpu().numpy() - ne_o).max() <= REL * np.abs(ne_o).max()
+        _within_rel(np.abs(est.double().cpu().numpy() - ne_o).max(), np.abs(ne_o).max())
     r_max = 1e-6
     print(f"[gfp wide valid] weighted={weighted}", flush=True)
     out, _, resid, _, _ = ops.gfp_level_dppr(csr, leaves, ALPHA, r_max, 10000, want_resid=True)
@@ -142,7 +157,7 @@ def test_rows_gathered_by_a_whole_wave(ops, weighted):
     got = out.double().cpu().numpy()
     assert np.all(R <= d[None, :] * r_max * (1 + 1e-5))
     err = O.gfp_error_term(pi_d, leaves, R, d)
-    assert np.abs(got + err - L).max() <= REL * np.abs(L).max()
+    _within_rel(np.abs(got + err - L).max(), np.abs(L).max())
     bound = r_max * np.array([d[F].mean() for F in leaves])
     tol = REL * np.abs(L).max()
     assert np.all(L - got >= -tol) and np.all(L - got <= bound[None, :] + tol)
@@ -160,9 +175,9 @@ def test_round_cap_keeps_the_invariant(ops):
         from paper_2112_14944_amd import _lib
         assert st == _lib.PPR_ENOCONV and rounds == cap
         err = O.gfp_error_term(pi_d, leaves, resid.double().cpu().numpy(), d)
-        assert np.abs(out.double().cpu().numpy() + err - L).max() <= REL * np.abs(L).max()
+        _within_rel(np.abs(out.double().cpu().numpy() + err - L).max(), np.abs(L).max())
         e_o, R_o, _, _, _ = O.group_forward_push_rounds(W, leaves, ALPHA, 1e-9, cap)
-        assert np.abs(out.double().cpu().numpy() - e_o).max() <= REL * np.abs(e_o).max()
+        _within_rel(np.abs(out.double().cpu().numpy() - e_o).max(), np.abs(e_o).max())
 
 
 def test_isolated_leaves_and_outside_nodes(ops):
@@ -181,7 +196,7 @@ def test_isolated_leaves_and_outside_nodes(ops):
     assert np.all(R[:, n - 5:] == 0)
     got = out.double().cpu().numpy()
     err = O.gfp_error_term(pi_d, leaves, R, d)
-    assert np.abs(got + err - L).max() <= REL * np.abs(L).max()
+    _within_rel(np.abs(got + err - L).max(), np.abs(L).max())
 
 
 def test_invalid_leaf_lists_are_rejected(ops):
@@ -268,12 +283,12 @@ def test_backward_zero_threshold_is_the_truncated_series(ops, n, blocks, k_ragge
         ppr_T, _, _ = O.ppr_power_iteration(P, np.arange(n), ALPHA, fixed_iters=T)
         want = O.level_dppr(ppr_T * d[:, None], leaves)[:, targets]
         got = out.double().cpu().numpy()
-        assert np.abs(got[:, targets] - want).max() <= REL * np.abs(want).max()
+        _within_rel(np.abs(got[:, targets] - want).max(), np.abs(want).max())
         others = [j for j in range(k) if j not in targets]
         assert np.all(got[:, others] == 0)  # untouched columns of the zeroed output
         e_o, R_o, ne_o, _, _ = O.group_backward_push_rounds(W, leaves, targets, ALPHA, 0.0, T)
-        assert np.abs(est.double().cpu().numpy() - ne_o).max() <= REL * np.abs(ne_o).max()
-        assert np.abs(resid.double().cpu().numpy() - R_o).max() <= REL * max(np.abs(R_o).max(), 1e-30)
+        _within_rel(np.abs(est.double().cpu().numpy() - ne_o).max(), np.abs(ne_o).max())
+        _within_rel(np.abs(resid.double().cpu().numpy() - R_o).max(), max(np.abs(R_o).max(), 1e-30))
 
 
 @pytest.mark.parametrize("weighted", [False, True])
@@ -289,7 +304,7 @@ def test_backward_result_is_valid(ops, weighted):
     R = resid.double().cpu().numpy()
     assert np.all(R <= th.astype(np.float32).astype(np.float64)[:, None] * (1 + 1e-6))
     err = O.gbp_error_term(ppr, leaves, targets, R, d)
-    assert np.abs(got + err - L[:, targets]).max() <= REL * np.abs(L).max()
+    _within_rel(np.abs(got + err - L[:, targets]).max(), np.abs(L).max())
     means = np.array([d[F].mean() for F in leaves])
     bound = means[:, None] * th[None, :]
     tol = REL * np.abs(L).max()
@@ -388,11 +403,11 @@ def test_overlapping_and_repeated_leaves(ops):
         out, est, resid, _, _ = ops.gfp_level_dppr(csr, leaves, ALPHA, 0.0, T, want_est=True, want_resid=True,
                                                    allow_noconv=True)
         e_o, R_o, ne_o, _, _ = O.group_forward_push_rounds(W, leaves, ALPHA, 0.0, T)
-        assert np.abs(out.double().cpu().numpy() - e_o).max() <= REL * np.abs(e_o).max()
-        assert np.abs(resid.double().cpu().numpy() - R_o).max() <= REL * np.abs(R_o).max()
+        _within_rel(np.abs(out.double().cpu().numpy() - e_o).max(), np.abs(e_o).max())
+        _within_rel(np.abs(resid.double().cpu().numpy() - R_o).max(), np.abs(R_o).max())
         bo, _, _, _, _ = ops.gbp_level_dppr(csr, leaves, [0, 1, 2], 0.0, ALPHA, T, allow_noconv=True)
         b_o, _, _, _, _ = O.group_backward_push_rounds(W, leaves, [0, 1, 2], ALPHA, 0.0, T)
-        assert np.abs(bo.double().cpu().numpy() - b_o).max() <= REL * np.abs(b_o).max()
+        _within_rel(np.abs(bo.double().cpu().numpy() - b_o).max(), np.abs(b_o).max())
 
 
 # ------------------------------------- receive marks (grids of > 8192 blocks)
@@ -430,18 +445,18 @@ def test_receive_marks_match_the_truncated_series(ops, weighted):
                                                          want_resid=True, allow_noconv=True)
         assert rounds == T
         e_o, R_o, ne_o, _, _ = O.group_forward_push_rounds(W, leaves, ALPHA, 0.0, T)
-        assert np.abs(out.double().cpu().numpy() - e_o).max() <= REL * np.abs(e_o).max()
-        assert np.abs(est.double().cpu().numpy() - ne_o).max() <= REL * np.abs(ne_o).max()
-        assert np.abs(resid.double().cpu().numpy() - R_o).max() <= REL * np.abs(R_o).max()
+        _within_rel(np.abs(out.double().cpu().numpy() - e_o).max(), np.abs(e_o).max())
+        _within_rel(np.abs(est.double().cpu().numpy() - ne_o).max(), np.abs(ne_o).max())
+        _within_rel(np.abs(resid.double().cpu().numpy() - R_o).max(), np.abs(R_o).max())
     for T in (2, 4):
         print(f"[gfp marks] weighted={weighted} backward T={T}", flush=True)
         bo, best, bres, rounds, _ = ops.gbp_level_dppr(csr, leaves, targets, 0.0, ALPHA, T, want_est=True,
                                                        want_resid=True, allow_noconv=True)
         assert rounds == T
         b_o, bR_o, bne_o, _, _ = O.group_backward_push_rounds(W, leaves, targets, ALPHA, 0.0, T)
-        assert np.abs(bo.double().cpu().numpy() - b_o).max() <= REL * np.abs(b_o).max()
-        assert np.abs(best.double().cpu().numpy() - bne_o).max() <= REL * np.abs(bne_o).max()
-        assert np.abs(bres.double().cpu().numpy() - bR_o).max() <= REL * np.abs(bR_o).max()
+        _within_rel(np.abs(bo.double().cpu().numpy() - b_o).max(), np.abs(b_o).max())
+        _within_rel(np.abs(best.double().cpu().numpy() - bne_o).max(), np.abs(bne_o).max())
+        _within_rel(np.abs(bres.double().cpu().numpy() - bR_o).max(), np.abs(bR_o).max())
 
 
 def test_receive_marks_keep_residue_and_stopping_rule(ops):

@@ -12,6 +12,23 @@ from gpu_util import get_ops
 pytestmark = pytest.mark.gpu
 
 CG_TOL = 1e-7
+# Bar for one exact step, relative to the layout's scale.  L^w of a k-node
+# layout is the Laplacian of the complete graph with weights Delta^-2, so its
+# nonzero eigenvalues lie in [k w_min, k w_max] and its condition number on
+# the centred subspace is at most (Delta_max / Delta_min)^2 <= (ln k)^2 for
+# PDist values in [2, 2 ln k] (about 60 at k = 2304).  CG stopped at relative
+# residual CG_TOL = 1e-7 in FP32 leaves a relative error of at most that
+# condition number times (CG_TOL + a few u), below 1e-5 (the largest ratio
+# measured on MI355X over these tests is 6.7e-7).
+STEP_REL = 1e-5
+WORST = [0.0]
+
+
+def _step_close(err, scale, floor=0.0):
+    ratio = (float(err) - floor) / float(scale)
+    WORST[0] = max(WORST[0], ratio)
+    print(f"[exact rel] {ratio:.3e} (worst so far {WORST[0]:.3e})", flush=True)
+    assert ratio <= STEP_REL, ratio
 
 
 @pytest.fixture(scope="module")
@@ -35,7 +52,7 @@ def test_exact_step_matches_pseudo_inverse(ops, k):
     x, iters = ops.layout_step_exact(_t(D), _t(Y), cg_tol=CG_TOL)
     want = O.majorization_step(Y.astype(np.float64), D.astype(np.float64))
     got = x.double().cpu().numpy()
-    assert np.abs(got - want).max() <= 1e-4 * _scale(want), (np.abs(got - want).max(), _scale(want), iters)
+    _step_close(np.abs(got - want).max(), _scale(want))
     assert 0 < iters < 1000
     np.testing.assert_allclose(got.mean(axis=0), 0.0, atol=1e-5 * _scale(want))
 
@@ -55,7 +72,7 @@ def test_exact_steps_from_a_real_pdist_never_increase_stress(ops):
         x, iters = ops.layout_step_exact(delta, x, cg_tol=CG_TOL)
         got = x.double().cpu().numpy()
         want = O.majorization_step(X, D)
-        assert np.abs(got - want).max() <= 1e-4 * _scale(want), step
+        _step_close(np.abs(got - want).max(), _scale(want))
         s = O.stress(got, D)
         assert s <= s_prev * (1 + 1e-6), (step, s, s_prev)
         s_prev = s
@@ -65,7 +82,7 @@ def test_planted_layout_is_a_fixed_point(ops):
     P, Dp = synth.planted_layout_distances(40, synth.BASE_SEED + 7)
     Pc = (P - P.mean(axis=0)).astype(np.float32)
     x, _ = ops.layout_step_exact(_t(Dp), _t(Pc), cg_tol=CG_TOL)
-    assert np.abs(x.double().cpu().numpy() - Pc).max() <= 1e-4 * _scale(Pc)
+    _step_close(np.abs(x.double().cpu().numpy() - Pc).max(), _scale(Pc))
 
 
 def test_coincident_points_and_converged_start(ops):
@@ -78,7 +95,7 @@ def test_coincident_points_and_converged_start(ops):
     got = x.double().cpu().numpy()
     assert np.all(np.isfinite(got))
     want = O.majorization_step(Y.astype(np.float64), D.astype(np.float64))
-    assert np.abs(got - want).max() <= 1e-4 * _scale(want)
+    _step_close(np.abs(got - want).max(), _scale(want))
     # a start that already solves its system stops before the first iteration
     x2, iters = ops.layout_step_exact(_t(D), x, cg_tol=1.0)
     assert iters == 0
@@ -127,7 +144,7 @@ def test_exact_step_tiny_layouts(ops, k):
     x, _ = ops.layout_step_exact(_t(D), _t(Y), cg_tol=CG_TOL)
     want = O.majorization_step(Y.astype(np.float64), D.astype(np.float64))
     got = x.double().cpu().numpy()
-    assert np.abs(got - want).max() <= 1e-4 * max(_scale(want), 1e-30) + 1e-7
+    _step_close(np.abs(got - want).max(), max(_scale(want), 1e-30), 1e-7)
 
 
 # ------------------------------------------- batch form (one block per subgraph)
@@ -159,7 +176,7 @@ def test_batch_exact_step_matches_pseudo_inverse(ops):
         a, b = int(gb.node_off[g]), int(gb.node_off[g + 1])
         want = O.majorization_step(Ys[g].astype(np.float64), Ds[g].astype(np.float64))
         err = np.abs(got[a:b] - want).max()
-        assert err <= 1e-4 * max(_scale(want), 1e-30) + 1e-7, (n, err, iters[g])
+        _step_close(err, max(_scale(want), 1e-30), 1e-7)
         assert 0 <= iters[g] < 1000
 
 
@@ -232,5 +249,5 @@ def test_batch_exact_step_on_the_batch_pipeline_output(ops):
         a, b = int(gb.node_off[g]), int(gb.node_off[g + 1])
         D = ops.graph_block(gb, bufs["delta"], g).double().cpu().numpy()
         want = O.majorization_step(xs[a:b], D)
-        assert np.abs(got[a:b] - want).max() <= 1e-4 * _scale(want), g
+        _step_close(np.abs(got[a:b] - want).max(), _scale(want))
         assert O.stress(got[a:b], D) <= O.stress(xs[a:b], D) * (1 + 1e-6), g
