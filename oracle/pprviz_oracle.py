@@ -322,7 +322,22 @@ def pipeline_forward(n, eu, ev, w, X, alpha, iters, n_clamp=None):
     return dict(W=W, d=d, P=P, Pi=Pi, pi_d=pid, Delta=D, loss=L, T=T, resid=resid)
 
 
-def grad_weights(n, eu, ev, w, X, alpha, iters, n_clamp=None, adjoint_iters="same"):
+def kink_pairs(pi_d, n_clamp, band):
+    """Pairs i < j whose 1 - ln z_ij lies within ``band`` of a clamp bound of
+    Eq. eq:pprdist (2 or 2 ln n_clamp).  The loss has a kink there; a path
+    that evaluates z in lower precision may take either side of it."""
+    pi_d = np.asarray(pi_d, dtype=np.float64)
+    z = pi_d + pi_d.T
+    hi = 2.0 * math.log(n_clamp)
+    raw = np.full_like(z, np.inf)
+    pos = z > 0
+    raw[pos] = 1.0 - np.log(z[pos])
+    near = (np.abs(raw - 2.0) < band) | (np.abs(raw - hi) < band)
+    i, j = np.nonzero(np.triu(near, 1))
+    return np.stack([i, j], axis=1)
+
+
+def grad_weights(n, eu, ev, w, X, alpha, iters, n_clamp=None, adjoint_iters="same", kink_band=None):
     """dL/dw_e for every undirected edge e, and dL/dX, FP64.
 
     Chain rule through the pipeline (all-pairs, rows = sources):
@@ -335,12 +350,21 @@ def grad_weights(n, eu, ev, w, X, alpha, iters, n_clamp=None, adjoint_iters="sam
       edge {u,v}: arc u->v + arc v->u  (one weight shared by both arcs).
     The PPR Jacobian used is that of the converged PPR (implicit function)
     evaluated at the truncated estimate and a truncated adjoint; it differs
-    from the derivative of the truncated forward by O((1-alpha)^iters)."""
+    from the derivative of the truncated forward by O((1-alpha)^iters).
+    With ``kink_band``, the pairs of kink_pairs(pi_d, n_clamp, kink_band) take
+    dDelta/dz = 0 (the one-sided derivative of the clamped side); they are
+    returned as "kink_pairs"."""
     f = pipeline_forward(n, eu, ev, w, X, alpha, iters, n_clamp)
     nc = n if n_clamp is None else n_clamp
     D, Pi, pid, d, P, W = f["Delta"], f["Pi"], f["pi_d"], f["d"], f["P"], f["W"]
     gD = grad_delta_pair(X, D)
-    Gd = gD * pdist_dz(pid, nc)
+    dz = pdist_dz(pid, nc)
+    kinks = np.zeros((0, 2), dtype=np.int64)
+    if kink_band is not None:
+        kinks = kink_pairs(pid, nc, kink_band)
+        dz[kinks[:, 0], kinks[:, 1]] = 0.0
+        dz[kinks[:, 1], kinks[:, 0]] = 0.0
+    Gd = gD * dz
     Gb = d[:, None] * Gd
     dd = (Gd * Pi).sum(axis=1)
     A = adjoint_solve(P, alpha, Gb, iters=None if adjoint_iters is None else
@@ -357,7 +381,7 @@ def grad_weights(n, eu, ev, w, X, alpha, iters, n_clamp=None, adjoint_iters="sam
     gw = arc(eu, ev) + arc(ev, eu)
     gx = grad_x(X, D)
     return dict(grad_w=gw, grad_x=gx, loss=f["loss"], Delta=D, pi_d=pid, Pi=Pi,
-                grad_pi_d=Gd, adjoint=A, dQ=dQ, d=d)
+                grad_pi_d=Gd, adjoint=A, dQ=dQ, d=d, kink_pairs=kinks)
 
 
 def central_difference(fun, x0, idx, h):

@@ -362,6 +362,37 @@ def test_weight_gradient_central_difference():
     np.testing.assert_allclose(res["grad_x"].ravel(), fdx, rtol=1e-6, atol=1e-8)
 
 
+def test_weight_gradient_with_kink_pairs_frozen():
+    # kink_band takes dDelta/dz = 0 for the pairs near a clamp bound: that is
+    # the gradient of the loss whose Delta at those pairs does not follow w.
+    # A wide band catches several pairs here; the central differences freeze
+    # those Delta entries at their unperturbed values.
+    n, eu, ev, w = _weighted_small(seed=25, n=14)
+    X = synth.uniform_layout(n, 26).astype(np.float64) * 3
+    iters = 160
+    base = O.pipeline_forward(n, eu, ev, w, X, ALPHA, iters)
+    z = base["pi_d"] + base["pi_d"].T
+    off = ~np.eye(n, dtype=bool)
+    band = float(np.sort(np.abs(1.0 - np.log(z[off]) - 2.0))[10]) + 1e-9
+    res = O.grad_weights(n, eu, ev, w, X, ALPHA, iters, kink_band=band)
+    kp = res["kink_pairs"]
+    assert 3 <= len(kp) < n * (n - 1) // 2 and np.all(kp[:, 0] < kp[:, 1])
+    raw = 1.0 - np.log(z[kp[:, 0], kp[:, 1]])
+    assert np.all(np.abs(raw - 2.0) < band)
+    D0 = base["Delta"]
+
+    def loss_frozen(wv):
+        D = O.pipeline_forward(n, eu, ev, wv, X, ALPHA, iters)["Delta"].copy()
+        D[kp[:, 0], kp[:, 1]] = D0[kp[:, 0], kp[:, 1]]
+        D[kp[:, 1], kp[:, 0]] = D0[kp[:, 1], kp[:, 0]]
+        return O.stress(X, D)
+
+    fd = O.central_difference(loss_frozen, w, list(range(len(w))), 1e-6)
+    np.testing.assert_allclose(res["grad_w"], fd, rtol=1e-5, atol=1e-8)
+    # and it differs from the plain gradient (the frozen pairs did contribute)
+    assert np.abs(res["grad_w"] - O.grad_weights(n, eu, ev, w, X, ALPHA, iters)["grad_w"]).max() > 1e-6
+
+
 def test_weight_gradient_euler_identity():
     # scaling every weight by c keeps P, multiplies pi_d by c and shifts every
     # unclamped Delta by -ln c: sum_e w_e dL/dw_e = -sum_{i<j unclamped} dL/dDelta_ij
