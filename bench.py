@@ -69,49 +69,88 @@ def traffic_from_profiles(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(graphs, sample_count=8):
-    """The FP64 oracle (unchanged) on a stratified sample of the batch: the
-    subgraphs at evenly spaced size quantiles, each through all-pairs PPR,
-    PDist and 200 Jacobi sweeps.  Returns subgraphs/s on this host."""
+def _oracle_subgraph(args):
+    """One sampled subgraph through the FP64 oracle (run in a worker process
+    with its BLAS pool limited to one thread): all-pairs PPR, PDist and the
+    Jacobi sweeps.  Returns the seconds it took."""
+    g, seed = args
     import oracle as O
     import synth
+
+    t0 = time.perf_counter()
+    W = O.weight_matrix(g.n, g.eu, g.ev)
+    d = O.degrees(W)
+    src = np.arange(g.n)
+    est, _, _ = O.ppr_power_iteration(O.transition(W), src, ALPHA, tol=TOL)
+    D = O.pdist(O.dppr(est, d, src), g.n)
+    X = synth.uniform_layout(g.n, seed).astype(np.float64)
+    for _ in range(STRESS_ITERS):
+        X = O.jacobi_step(X, D)
+    return time.perf_counter() - t0
+
+
+def _one_blas_thread():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(graphs, sample_count=32, max_procs=16):
+    """The FP64 oracle (unchanged) on a stratified sample of the batch, one
+    subgraph per task in a pool of worker processes, one per host core (at
+    most 16, the host share of one GPU), each with a one-thread BLAS pool.
+    The sample is the subgraphs at evenly spaced size quantiles, each through
+    all-pairs PPR, PDist and 200 Jacobi sweeps.  Returns subgraphs/s of the
+    whole pool (sample size over wall time); ``balanced_value`` is the rate
+    with the worker time spread evenly over the processes, which is what the
+    pool would approach on the whole batch."""
+    import multiprocessing as mp
 
     sizes = np.array([g.n for g in graphs])
     order = np.argsort(sizes, kind="stable")
     qs = (np.arange(sample_count) + 0.5) / sample_count
     pick = order[np.minimum((qs * len(order)).astype(int), len(order) - 1)]
+    procs = max(1, min(max_procs, len(os.sched_getaffinity(0)), len(pick)))
+    # largest first, so that the pool's tail is short
+    tasks = [(graphs[gi], int(gi)) for gi in sorted(pick, key=lambda i: -sizes[i])]
+    ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
-    for gi in pick:
-        g = graphs[gi]
-        W = O.weight_matrix(g.n, g.eu, g.ev)
-        d = O.degrees(W)
-        src = np.arange(g.n)
-        est, _, _ = O.ppr_power_iteration(O.transition(W), src, ALPHA, tol=TOL)
-        D = O.pdist(O.dppr(est, d, src), g.n)
-        X = synth.uniform_layout(g.n, int(gi)).astype(np.float64)
-        for _ in range(STRESS_ITERS):
-            X = O.jacobi_step(X, D)
+    with ctx.Pool(procs, initializer=_one_blas_thread) as pool:
+        per = pool.map(_oracle_subgraph, tasks, chunksize=1)
     dt = time.perf_counter() - t0
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    except Exception:
-        threads = 1
-    return dict(value=len(pick) / dt, unit="subgraphs/s", cores=int(threads), kind="oracle",
-                sample=f"{len(pick)} subgraphs at evenly spaced size quantiles (n={sorted(int(sizes[i]) for i in pick)}), "
-                       f"all-pairs PPR T=86 + PDist + {STRESS_ITERS} FP64 Jacobi sweeps, {dt:.1f} s",
-                seconds=dt, host_cpus=len(os.sched_getaffinity(0)))
+    return dict(value=len(pick) / dt, unit="subgraphs/s", cores=procs, kind="oracle",
+                balanced_value=procs * len(pick) / float(sum(per)),
+                sample=f"{len(pick)} subgraphs at evenly spaced size quantiles (n from {int(sizes[pick].min())} to "
+                       f"{int(sizes[pick].max())}), each all-pairs PPR T=86 + PDist + {STRESS_ITERS} FP64 Jacobi "
+                       f"sweeps, in {procs} worker processes with one BLAS thread each; {dt:.1f} s wall, "
+                       f"{sum(per):.1f} s of worker time",
+                seconds=dt, worker_seconds=float(sum(per)), host_cpus=len(os.sched_getaffinity(0)),
+                cpu_model=host_cpu_model())
 
 
 def stage_rooflines(gb, T, ms):
     """Roofline records of the batched stages from the library's stage times.
 
-    PPR (three persistent launches, one per tile class, timed together):
-    algorithmic bytes per push are those a streaming SpMM must move, per
+    PPR (three persistent launches, one per tile class, timed together): the
+    tile keeps X in LDS and is bound by VALU issue, so its roofline is FP32
+    adds (one per arc, source column and push) against the plain FP32 add
+    peak, 256 CUs x 64 lanes x 2.4 GHz (no packed FP32).  The bytes a
+    streaming SpMM would move are kept beside it (hbm_model): per push and
     subgraph 8 n^2 (read X_t, write X_t+1, S = n sources) + 4 nnz + 8 n + 4
     (column indices, row pointers, 1/d); T - 1 pushes follow the initial
-    iterate.  The tile keeps X on chip, so its HBM traffic is far below this;
-    its own limit is the LDS gather, reported as FP32 adds per second.
+    iterate.
     Layout (a pair-tile launch plus a combine launch per sweep): Delta is
     symmetric, so a sweep needs one triangle of 1/Delta with its diagonal,
     2 n (n + 1) bytes, plus 20 n of positions in and out and weight sums per
@@ -129,12 +168,15 @@ def stage_rooflines(gb, T, ms):
     layout_bytes = float((2.0 * sizes * (sizes + 1.0) + 20.0 * sizes).sum())
     ppr_ms, layout_ms = ms[1], ms[3]
     lay_launch_ms = layout_ms / (STRESS_ITERS + 1)
-    st_ppr = dict(kernel="batch_ppr_kernel", ms=ppr_ms, launches=3, bound="hbm", unit="GB/s",
-                  achieved=ppr_bytes / (ppr_ms * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
-                  work=f"{ppr_bytes:.4g} B over {pushes} pushes (X read and written once per push, plus CSR)",
-                  adds_per_s=ppr_adds / (ppr_ms * 1e-3), adds=ppr_adds,
-                  alu_peak_adds_per_s=PEAK_FP32_ADDS, alu_frac=ppr_adds / (ppr_ms * 1e-3) / PEAK_FP32_ADDS)
-    st_ppr["frac"] = st_ppr["achieved"] / PEAK_HBM_GBS
+    adds_per_s = ppr_adds / (ppr_ms * 1e-3)
+    hbm_ach = ppr_bytes / (ppr_ms * 1e-3) / 1e9
+    st_ppr = dict(kernel="batch_ppr_kernel", ms=ppr_ms, launches=3, bound="alu", unit="TFLOP/s",
+                  achieved=adds_per_s / 1e12, peak=PEAK_FP32_ADDS / 1e12, frac=adds_per_s / PEAK_FP32_ADDS,
+                  work=f"{ppr_adds:.4g} FP32 adds over {pushes} pushes (one per arc, source column and push)",
+                  adds_per_s=adds_per_s, adds=ppr_adds,
+                  hbm_model=dict(unit="GB/s", achieved=hbm_ach, peak=PEAK_HBM_GBS, frac=hbm_ach / PEAK_HBM_GBS,
+                                 work=f"{ppr_bytes:.4g} B over {pushes} pushes (X read and written once per "
+                                      f"push, plus CSR), the bytes a streaming SpMM would move"))
     st_lay = dict(kernel="batch_pair_kernel", ms=layout_ms, launches=2 * (STRESS_ITERS + 1), bound="hbm",
                   unit="GB/s", achieved=layout_bytes / (lay_launch_ms * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
                   work=f"{layout_bytes:.4g} B per sweep (one triangle of 1/Delta, X in and out, weight sums)")
@@ -146,37 +188,68 @@ def stage_rooflines(gb, T, ms):
     return dict(plan_ms=ms[0], ppr=st_ppr, pdist_ms=ms[2], layout=st_lay)
 
 
-def spmm_all_pairs(ops, dev, n=20000, gamma=2.5, avg_degree=20, tol=1e-7, reps=2):
-    """The multi-source SpMM of a single large graph: all-pairs PPR on a
-    Chung-Lu graph, n = 20000, exponent 2.5, mean degree 20, to L1 1e-7, one
-    whole ppr_matrix call (row order, arc deal, T pushes, DPPR written).  At
-    this size the library keeps 2 source columns of every node in LDS
-    (ppr_mid_kernel).  Algorithmic bytes per push, as for any SpMM that keeps
-    X in HBM: 8 n S (X read and written once, S = n sources) + 4 nnz + 8 (n + 1)."""
+def spmm_all_pairs(ops, dev, n=20000, gamma=2.5, avg_degree=20, tol=1e-7, reps=2, sweeps=500):
+    """The single large graph end to end: all-pairs PPR on a Chung-Lu graph,
+    n = 20000, exponent 2.5, mean degree 20, to L1 1e-7 (one whole
+    ppr_matrix call: row order, arc deal, T pushes, DPPR written; at this size
+    the library keeps 2 source columns of every node in LDS, ppr_mid_kernel),
+    then PDist and `sweeps` Jacobi sweeps of the 20000-node layout
+    (layout_step, one launch per sweep), each stage timed with HIP events on
+    the stream the library launches on.  Algorithmic bytes: per push, as for
+    any SpMM that keeps X in HBM, 8 n S (X read and written once, S = n
+    sources) + 4 nnz + 8 (n + 1); PDist reads and writes n^2 floats; a sweep
+    reads Delta (4 n^2 bytes).  Sweep FLOPs by the 15-per-ordered-pair
+    convention."""
     import torch
     import synth
 
     g = synth.chung_lu(n, gamma, avg_degree, synth.BASE_SEED + 2)
     csr = ops.Csr.from_graph(g, dev)
     src = torch.arange(n, dtype=torch.int32, device=dev)
-    best = None
-    for _ in range(reps):
-        torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        _, dppr, T, _ = ops.ppr_matrix(csr, src, None, alpha=ALPHA, tol=tol, want_ppr=False, want_dppr=True)
-        e1.record()
         torch.cuda.synchronize()
-        t = e0.elapsed_time(e1)
+        e0.record(stream)
+        out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1)
+
+    best = None
+    dppr = None
+    T = 0
+    for _ in range(reps):
+        dppr = None
+        (_, dppr, T, _), t = timed(lambda: ops.ppr_matrix(csr, src, None, alpha=ALPHA, tol=tol, want_ppr=False,
+                                                         want_dppr=True))
         best = t if best is None else min(best, t)
-        del dppr
+    delta, t_pd = timed(lambda: ops.pdist(dppr, n))
+    del dppr
+    x0 = torch.as_tensor(synth.uniform_layout(n, 41), device=dev)
+    s0 = ops.stress_eval(delta, x0).item()
+    x, t_lay = timed(lambda: ops.layout(delta, x0, sweeps))
+    s1 = ops.stress_eval(delta, x).item()
+    del delta
     nnz = int(g.col_idx.shape[0])
     alg = (T - 1) * (8.0 * n * n + 4.0 * nnz + 8.0 * (n + 1))
+    pd_bytes = 8.0 * n * n
+    lay_bytes = sweeps * 4.0 * n * n
+    lay_flops = sweeps * 15.0 * n * (n - 1.0)
     return dict(workload=f"chung_lu n={n} gamma={gamma} mean degree {avg_degree}, all {n} sources, "
-                         f"L1 {tol:g} (T={T}), whole ppr_matrix call", kernel="ppr_mid_kernel", ms=best,
-                bound="hbm", unit="GB/s", achieved=alg / (best * 1e-3) / 1e9, peak=PEAK_HBM_GBS,
-                frac=alg / (best * 1e-3) / 1e9 / PEAK_HBM_GBS, work=f"{alg:.4g} B over {T - 1} pushes", nnz=nnz)
+                         f"L1 {tol:g} (T={T}), PDist, {sweeps} Jacobi sweeps from U[-1,1]^2",
+                kernel="ppr_mid_kernel", ms=best, bound="hbm", unit="GB/s", achieved=alg / (best * 1e-3) / 1e9,
+                peak=PEAK_HBM_GBS, frac=alg / (best * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                work=f"{alg:.4g} B over {T - 1} pushes", nnz=nnz,
+                pdist=dict(kernel="pdist_kernel", ms=t_pd, bound="hbm", unit="GB/s",
+                           achieved=pd_bytes / (t_pd * 1e-3) / 1e9, frac=pd_bytes / (t_pd * 1e-3) / 1e9 / PEAK_HBM_GBS),
+                layout=dict(kernel="layout_rows_kernel", sweeps=sweeps, ms=t_lay, ms_per_sweep=t_lay / sweeps,
+                            bound="hbm", unit="GB/s", achieved=lay_bytes / (t_lay * 1e-3) / 1e9,
+                            frac=lay_bytes / (t_lay * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                            tflops=lay_flops / (t_lay * 1e-3) / 1e12, stress_before=s0, stress_after=s1),
+                total_ms=best + t_pd + t_lay)
 
 
 def spmm_large(ops, dev, n=1_000_000, gamma=2.2, avg_degree=30, n_src=4096, tol=1e-6, reps=2):
@@ -471,9 +544,20 @@ def counters_pass(ops, b, x0, dev):
     bufs = b.buffers(x0)
     ms = ops.pprviz_batch_profile(b, bufs, alpha=ALPHA, tol=TOL, stress_iters=STRESS_ITERS)
     log(f"eager pass stage ms {ms}")
+    _, iters, _ = ops.batch_step_exact(b, bufs["delta"], bufs["x_out"], cg_tol=1e-6)
+    torch.cuda.synchronize()
+    log(f"batched exact step, CG iterations mean {float(iters.float().mean()):.2f}")
     del bufs
-    sp = spmm_all_pairs(ops, dev, reps=1)
+    sp = spmm_all_pairs(ops, dev, reps=1, sweeps=1)
     log(f"all-pairs SpMM (n = 20000) {sp['ms']:.1f} ms")
+    calibration_copy()
+
+
+def calibration_copy():
+    """A plain 1 GiB device-to-device copy: its FETCH_SIZE / WRITE_SIZE give
+    the counters' scale."""
+    import torch
+
     a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     c = torch.empty_like(a)
     torch.cuda.synchronize()
@@ -500,6 +584,9 @@ def main():
                     help="run only the level-l DPPR leg (10^6-node graph) and print its JSON object")
     ap.add_argument("--counters", action="store_true",
                     help="one eager batched pass plus a 1 GiB calibration copy (for rocprofv3 --pmc), no timing")
+    ap.add_argument("--counters-large", action="store_true",
+                    help="one 4096-source ppr_matrix call on the 10^6-node graph plus the 1 GiB calibration copy "
+                         "(for rocprofv3 --pmc), no timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1 "
@@ -514,6 +601,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
+    if args.counters_large:
+        sp, _ = spmm_large(ops, dev, reps=1)
+        log(f"4096-source SpMM (n = 10^6): {sp['ms']:.1f} ms")
+        calibration_copy()
+        return
     if args.only_gfp:
         g_big = synth.chung_lu(1_000_000, 2.2, 30, synth.BASE_SEED + 4)
         gfp = gfp_level(ops, dev, g_big, ops.Csr.from_graph(g_big, dev), cpu=not args.no_cpu_baseline)
@@ -571,7 +663,8 @@ def main():
         roof = dict(kernel=dom["kernel"], bound=dom["bound"], achieved=dom["achieved"], peak=dom["peak"],
                     unit=dom["unit"], frac=dom["frac"], traffic=traffic)
         log(f"stages ms: plan {ms[0]:.2f} ppr {ms[1]:.2f} pdist {ms[2]:.2f} layout {ms[3]:.2f}; "
-            f"ppr {stages['ppr']['achieved']:.0f} GB/s ({stages['ppr']['adds_per_s'] / 1e12:.2f} T adds/s), "
+            f"ppr {stages['ppr']['adds_per_s'] / 1e12:.2f} T adds/s ({100 * stages['ppr']['frac']:.0f}% of the "
+            f"FP32 add peak; {stages['ppr']['hbm_model']['achieved']:.0f} GB/s by the SpMM byte model), "
             f"layout {stages['layout']['achieved']:.0f} GB/s, {stages['layout']['tflops']:.1f} TFLOP/s FP32 "
             f"({100 * stages['layout']['flop_frac']:.0f}% of the vector peak)")
 
@@ -645,7 +738,10 @@ def main():
     spmm = None
     if not args.no_spmm:
         spmm = spmm_all_pairs(ops, dev)
-        log(f"all-pairs SpMM (n = 20000): {spmm['ms']:.1f} ms, {spmm['achieved']:.0f} GB/s algorithmic")
+        log(f"all-pairs SpMM (n = 20000): {spmm['ms']:.1f} ms, {spmm['achieved']:.0f} GB/s algorithmic; PDist "
+            f"{spmm['pdist']['ms']:.2f} ms; {spmm['layout']['sweeps']} sweeps {spmm['layout']['ms']:.1f} ms "
+            f"({spmm['layout']['achieved']:.0f} GB/s), stress {spmm['layout']['stress_before']:.4g} -> "
+            f"{spmm['layout']['stress_after']:.4g}")
 
     spmm_big = None
     gfp = None
@@ -683,7 +779,8 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a sample ...")
         cpu = cpu_baseline(graphs)
-        log(f"oracle: {cpu['value']:.4f} subgraphs/s ({cpu['seconds']:.1f}s, {cpu['cores']} threads)")
+        log(f"oracle: {cpu['value']:.4f} subgraphs/s ({cpu['seconds']:.1f}s wall, {cpu['cores']} processes, "
+            f"{cpu['cpu_model']})")
 
     out = {
         "metric": "subgraphs laid out/sec (batched vs plain, same GPU) at PPR err<=1e-6; SpMM HBM GB/s",
