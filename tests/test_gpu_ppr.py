@@ -202,8 +202,9 @@ def test_chung_lu_20000_all_pairs_sampled(ops):
     # Chung-Lu n=20000, gamma 2.5, mean degree 20, all 20000 sources to L1
     # residual 1e-7 (T = 100): full FP32 n x n output; the oracle checks 48
     # sources (the 8 of highest degree, where pi_d(s, s) >= alpha d(s) is
-    # largest, and 40 seeded others), their PDist block, and one Jacobi step
-    # of those 48 rows of the full-size layout.
+    # largest, and 40 seeded others), their PDist block, the first and the
+    # 500th Jacobi sweep of those 48 rows of the full-size layout, and the
+    # stress trend over the 500 sweeps.
     g = synth.chung_lu(20000, 2.5, 20, synth.BASE_SEED + 2)
     n = g.n
     print(f"[chung-lu n=20000] n={n} nnz={g.nnz}", flush=True)
@@ -237,3 +238,20 @@ def test_chung_lu_20000_all_pairs_sampled(ops):
     got = x1[sidx].double().cpu().numpy()
     assert np.abs(got - want).max() <= STEP_REL * np.abs(X0).max()
     assert st.item() > 0 and np.isfinite(st.item())
+    # the workload's 500 sweeps: the stress of every 50th layout does not rise,
+    # and the 500th sweep, taken from the GPU's 499th layout, matches the
+    # oracle's Jacobi step on the sampled rows
+    x = x1
+    trend = [st.item()]
+    for done in range(1, 499, 50):
+        x = ops.layout(delta, x, min(50, 499 - done))
+        trend.append(ops.stress_eval(delta, x).item())
+    x499 = x
+    x500 = ops.layout(delta, x499, 1)
+    trend.append(ops.stress_eval(delta, x500).item())
+    print(f"[chung-lu n=20000] stress every 50 sweeps: {[round(t, 1) for t in trend]}", flush=True)
+    assert all(b <= a * (1 + 1e-6) for a, b in zip(trend, trend[1:])), trend
+    X499 = x499.double().cpu().numpy()
+    want500 = O.jacobi_rows(X499, Drows, sample)
+    got500 = x500[sidx].double().cpu().numpy()
+    assert np.abs(got500 - want500).max() <= STEP_REL * np.abs(X499).max()
