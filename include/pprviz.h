@@ -107,8 +107,8 @@ size_t ppr_matrix_workspace(const ppr_csr* g, int32_t n_src, int32_t n_tgt);
  * Kernel by size: n <= 2304 keeps a tile of sources in LDS; n <= 40831 keeps
  * 4, 2 or 1 source columns of every node in LDS (these two never move the
  * iterate through HBM); larger n streams the iterate through HBM.  On the
- * middle path a row that lists more than n arcs (repeated neighbours) can
- * exceed the workspace bound of its padded arc copy: the outputs and the
+ * first two paths a row that lists more than n arcs (repeated neighbours) can
+ * exceed the workspace bound of the padded arc copy: the outputs and the
  * residual are then NaN (PPR_ENONFINITE when resid_out is asked for).
  */
 ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src,
@@ -128,7 +128,7 @@ ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src,
  * Limit: the workspace ppr_matrix_workspace(g, n_src, n_tgt) would ask for
  * must fit ppr_matrix_noalloc_max_scratch() bytes (8 MiB), else the call
  * returns PPR_EUNSUPPORTED before any launch.  That covers, for example, the
- * LDS-resident path (n <= 2304) up to about 1.9 million arcs unweighted.
+ * LDS-resident path (n <= 2304) up to about 2 million arcs unweighted.
  *
  * The scratch is one array per GPU, held from the first call on that GPU
  * until the process ends (its device address is looked up once per device).

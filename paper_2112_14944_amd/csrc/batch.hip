@@ -251,6 +251,7 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t*
 struct BatchArgs {
     const int64_t* node_off;
     const int64_t* mat_off;
+    const int32_t* row_ptr;
     int32_t G;
     ResArgs r;  // graph-global fields; src/tgt null (all pairs), ppr_out null
 };
@@ -284,6 +285,7 @@ __global__ __launch_bounds__(kResThreads) void batch_ppr_kernel(BatchArgs b, Bat
         t.base = b.node_off[g];
         t.out_off = b.mat_off[g];
         t.ld = n;
+        res_graph_bases(t.base, b.row_ptr[t.base], b.row_ptr[t.base + n], g, n, t);
         res_tile<COLS, false>(t, b.r, L);
     }
 }
@@ -439,8 +441,8 @@ __global__ void copy_kernel(const float* __restrict__ a, float* __restrict__ b, 
 }
 
 struct BatchWs {
-    RowEnt* rows;
-    int32_t* col_r;  // arcs in bank-class order (bank_order_kernel)
+    ResSlot* slots;  // resident-tile slot tables (res_layout_kernel)
+    int32_t* col_r;  // arc copies in group layout
     float* deg;
     float* invd;
     float* inv;   // 1/Delta pool (zero diagonal)
@@ -455,8 +457,9 @@ struct BatchWs {
 template <typename Cursor>
 static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     BatchWs t;
-    t.rows = c.template take<RowEnt>((size_t)b->n_nodes);
-    t.col_r = c.template take<int32_t>((size_t)(b->nnz + (int64_t)kArcRowPad * b->n_nodes + kArcPad));
+    t.slots = c.template take<ResSlot>((size_t)(b->n_nodes + (int64_t)kResTabPad * b->n_graphs));
+    t.col_r = c.template take<int32_t>(
+        (size_t)(b->nnz + (int64_t)kResArcPerNode * b->n_nodes + (int64_t)kResArcPerGraph * b->n_graphs));
     t.deg = c.template take<float>((size_t)b->n_nodes);
     t.invd = c.template take<float>((size_t)b->n_nodes);
     // 1/Delta pool with rows padded to 32 floats: sum_g k (k + 31) <= pool + 31 n_nodes
@@ -520,8 +523,6 @@ static ppr_status batch_validate(const ppr_batch* b, float alpha, int32_t max_it
     if (!x0 || !x_out || x0 == x_out || !dppr_pool || !delta_pool) return PPR_EINVAL;
     if (b->max_n < 1 || b->pool_size < b->n_nodes) return PPR_EINVAL;
     if (b->max_n > kBatchMaxN) return PPR_EUNSUPPORTED;
-    // positions in the padded arc copy are int32
-    if (b->nnz + (int64_t)kArcRowPad * (b->n_nodes + 1) + kArcPad >= (int64_t)INT32_MAX) return PPR_EUNSUPPORTED;
     return PPR_OK;
 }
 
@@ -534,19 +535,18 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     const int G = b->n_graphs;
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[0], s));
     launch_degree(b->row_ptr, nullptr, b->n_nodes, w.deg, w.invd, s);
-    launch_row_table(b->row_ptr, b->col_idx, nullptr, b->node_off, 0, G, b->n_nodes, w.rows, w.col_r, nullptr, s);
+    launch_res_layout(b->row_ptr, b->col_idx, nullptr, w.invd, b->node_off, 0, G, w.slots, w.col_r, nullptr, s);
     hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, b->node_off, G, w.plan);
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[1], s));
 
     BatchArgs ba;
     ba.node_off = b->node_off;
     ba.mat_off = b->mat_off;
+    ba.row_ptr = b->row_ptr;
     ba.G = G;
-    ba.r.rows = w.rows;
-    ba.r.row_ptr = b->row_ptr;
-    ba.r.col_idx = w.col_r;
-    ba.r.weight = nullptr;
-    ba.r.invd = w.invd;
+    ba.r.slots = w.slots;
+    ba.r.arcs = w.col_r;
+    ba.r.warcs = nullptr;
     ba.r.deg = w.deg;
     ba.r.src = nullptr;
     ba.r.tgt = nullptr;

@@ -16,10 +16,11 @@ namespace pprviz {
 // taken, unless the streaming buffers are asked for as well.
 struct PprWs {
     RowEnt* rows;
+    ResSlot* slots;  // resident tile: slot table
     float* deg;
     float* invd;
     double* resid;
-    int32_t* col_r;  // resident tile: arcs in bank-class order
+    int32_t* col_r;  // resident tile: arc copy in group layout
     float* w_r;
     MidWs mid;       // mid-size kernel: plan and arc stream
     float* ya;       // streaming SpMM: iterate ping-pong
@@ -38,8 +39,9 @@ void ppr_ws_layout(Cursor& c, int n, int64_t nnz, bool weighted, int n_src, PprW
     const bool res = res_cols_for(n) != 0;
     const bool mid = mid_cols_for(n) != 0;
     if (res) {
-        t.col_r = c.template take<int32_t>((size_t)(nnz + (int64_t)kArcRowPad * n + kArcPad));
-        t.w_r = weighted ? c.template take<float>((size_t)(nnz + (int64_t)kArcRowPad * n + kArcPad)) : nullptr;
+        t.slots = c.template take<ResSlot>((size_t)n + kResTabPad);
+        t.col_r = c.template take<int32_t>((size_t)res_arc_words(nnz, n));
+        t.w_r = weighted ? c.template take<float>((size_t)res_arc_words(nnz, n)) : nullptr;
     }
     if (mid) {
         const int64_t groups = mid_stream_groups(n, nnz);
@@ -75,8 +77,8 @@ void launch_degree(const int32_t* row_ptr, const float* weight, int64_t n, float
 void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int32_t* tgt, int32_t n_tgt,
                  float alpha, int32_t T, float* ppr_out, float* dppr_out, const float* deg, const float* invd,
                  double* resid, const PprWs& w, hipStream_t s);
-void launch_row_table(const int32_t* row_ptr, const int32_t* col_idx, const float* weight,
-                      const int64_t* node_off, int32_t n_single, int32_t blocks, int64_t n_slots, RowEnt* table,
-                      int32_t* col_out, float* w_out, hipStream_t s);
+void launch_res_layout(const int32_t* row_ptr, const int32_t* col_idx, const float* weight, const float* invd,
+                       const int64_t* node_off, int32_t n_single, int32_t blocks, ResSlot* slots, int32_t* arcs,
+                       float* warcs, hipStream_t s);
 
 }  // namespace pprviz

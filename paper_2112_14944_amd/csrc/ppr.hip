@@ -27,19 +27,197 @@ __global__ void degree_kernel(const int32_t* __restrict__ row_ptr, const float* 
     invd[v] = (re > rs && d > 0.f) ? 1.0f / d : 1.0f;
 }
 
-// Row table of the resident tile: rows sorted by degree, longest first, ties
-// by row id; one block per graph.  rs/re locate the row in the tile's arc
-// copy, where global row v starts at row_ptr[v] + kArcRowPad v (room to pad
-// each row, see bank_order_kernel).
-__global__ __launch_bounds__(256) void row_table_kernel(const int32_t* __restrict__ row_ptr,
-                                                       const int64_t* __restrict__ node_off, int32_t n_single,
-                                                       RowEnt* __restrict__ table) {
+// Slot table and arc copy of the resident tile (group layout, see
+// ppr_core.hpp), one block per graph.
+//  1. Rows sorted by degree, longest first, ties by row id (bitonic sort of
+//     4096 keys in LDS; a graph of the resident tile has at most 2304 rows).
+//  2. Group g's length: its longest row (at least 1: a row without arcs gets
+//     its self arc) in 8-arc halves; chunk offsets by a prefix sum in sorted
+//     order.
+//  3. Arcs are dealt by LDS bank class.  One LDS cycle of the tile's
+//     16-byte reads serves M rows at once (M = 4, 2, 1 for 16, 32, 64
+//     columns: 64 bytes of each of 4 rows, 128 of 2, 256 of 1;
+//     res_conflict_set names them), and row u starts in bank class u mod M.
+//     One thread takes such a set of M rows and fills their positions m = 0,
+//     1, ... together: each row takes, among the classes no other row has
+//     taken at m, the one it holds most arcs of; a row with no such arc pads
+//     with the zero row of a free class (the tile has one zero row per class)
+//     as long as it can still fit its arcs, and otherwise takes a
+//     conflicting class.  Only the order of each row's arcs changes (and
+//     with it the order of the FP32 sum).  The copy holds each arc's LDS byte
+//     offset in the tile, (u - first node) * 4 COLS, not its node id.
+// A graph whose padded groups exceed its reserved region (possible only with
+// repeated arcs, when a row is longer than n) gets one half chunk per row
+// holding the row's own offset and a NaN scale, so that its outputs are NaN.
+// The rows of a group whose LDS reads are served in the same cycles.  A
+// 16-byte LDS read by a wave is served 16 lanes at a time, lanes grouped by
+// lane bit 5 and the parity of lane bits 2..4 (a probe of the patterns
+// across the 16 quads of a wave: quads {0,3,5,6} share cycles, as do
+// {1,2,4,7} and the same sets plus 8).  With 16 columns a quad is a row,
+// so those quad sets are the row sets; with 32 columns quads 2r and 2r+1
+// read the two halves of row r, and the rows whose halves meet in one
+// cycle set are {0,3} and {1,2} (and plus 4); with 64 columns one row fills
+// a cycle set.
+__device__ __forceinline__ void res_conflict_set(int M, int j, int rr[4]) {
+    if (M == 4) {
+        const int h = (j >> 1) * 8;
+        const bool odd = (j & 1) != 0;
+        rr[0] = h + (odd ? 1 : 0);
+        rr[1] = h + (odd ? 2 : 3);
+        rr[2] = h + (odd ? 4 : 5);
+        rr[3] = h + (odd ? 7 : 6);
+    } else if (M == 2) {
+        const int h = (j >> 1) * 4;
+        rr[0] = h + ((j & 1) ? 1 : 0);
+        rr[1] = h + ((j & 1) ? 2 : 3);
+        rr[2] = rr[3] = 0;
+    } else {
+        rr[0] = j;
+        rr[1] = rr[2] = rr[3] = 0;
+    }
+}
+
+// One set of M rows of a group (res_conflict_set), dealt together.
+struct ResDealSet {
+    int L;          // positions every row of the set fills (the group's length)
+    int words;      // entries per row over all its chunks
+    int32_t* ca;    // the group's chunk 0 in the arc copy
+    float* wa;      // same for the weights, or nullptr
+    int GW, n, stride;
+    int64_t base;
+    bool over;      // NaN layout: each row holds only its own offset
+    const int32_t* row_ptr;
+    const int32_t* col_idx;
+    const float* weight;
+};
+
+// Fills the set's rows position by position.  At position m the rows choose
+// in the order m, m+1, ... (mod M); each takes the free class it holds most
+// arcs of, pads with the zero row of a free class when it has none and can
+// still fit its arcs, and otherwise takes its largest class (a conflict).
+// Rows without arcs hold their own offset first; v[i] < 0 marks a dummy slot.
+template <int M>
+__device__ __forceinline__ void res_deal_set(const ResDealSet& d, const int rr[4], const int v[4]) {
+    auto at = [&](int m) { return (int64_t)(m >> 4) * 16 * d.GW + (m & 15); };
+    auto zero_row = [&](int c) { return (d.n + (((c - d.n) % M) + M) % M) * d.stride; };
+    auto put = [&](int i, int m, int off, float w) {
+        d.ca[16 * rr[i] + at(m)] = off;
+        if (d.wa) d.wa[16 * rr[i] + at(m)] = w;
+    };
+    int cnt[M][M], cur[M][M], rem[M], re[M];
+    bool fixed[M];  // rows written outside the deal (own offset first, or dummies)
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        rem[i] = 0;
+        re[i] = 0;
+        fixed[i] = false;
+#pragma unroll
+        for (int c = 0; c < M; ++c) cnt[i][c] = cur[i][c] = 0;
+        if (v[i] < 0) continue;
+        const int rs = d.row_ptr[d.base + v[i]];
+        re[i] = d.row_ptr[d.base + v[i] + 1];
+        if (d.over || re[i] == rs) {
+            put(i, 0, v[i] * d.stride, 1.f);
+            for (int m = 1; m < d.words; ++m) put(i, m, d.n * d.stride, 0.f);
+            fixed[i] = true;
+            continue;
+        }
+        rem[i] = re[i] - rs;
+#pragma unroll
+        for (int c = 0; c < M; ++c) cur[i][c] = re[i];
+        for (int e = re[i] - 1; e >= rs; --e) {
+            const int c = (int)((d.col_idx[e] - d.base) & (M - 1));
+#pragma unroll
+            for (int cc = 0; cc < M; ++cc)
+                if (cc == c) {
+                    ++cnt[i][cc];
+                    cur[i][cc] = e;
+                }
+        }
+    }
+    for (int mb = 0; mb < d.L; mb += M) {
+#pragma unroll
+        for (int s = 0; s < M; ++s) {
+            const int m = mb + s;
+            uint32_t taken = 0, placed = 0;
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int i = (s + k) % M;
+                if (fixed[i] || rem[i] == 0) continue;
+                int pick = -1, pany = -1, pickv = 0, panyv = 0;
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    const int x = cnt[i][c];
+                    if (x > panyv) {
+                        pany = c;
+                        panyv = x;
+                    }
+                    if (!(taken >> c & 1u) && x > pickv) {
+                        pick = c;
+                        pickv = x;
+                    }
+                }
+                placed |= 1u << i;
+                if (pick < 0 && rem[i] < d.L - m && taken != (1u << M) - 1u) {
+                    const int c = __builtin_ctz(~taken);
+                    taken |= 1u << c;
+                    put(i, m, zero_row(c), 0.f);
+                    continue;
+                }
+                if (pick < 0) pick = pany;
+                taken |= 1u << pick;
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    if (c != pick) continue;
+                    const int e = cur[i][c];
+                    put(i, m, (int)(d.col_idx[e] - d.base) * d.stride, d.weight ? d.weight[e] : 0.f);
+                    int f = e + 1;
+                    while (f < re[i] && (int)((d.col_idx[f] - d.base) & (M - 1)) != c) ++f;
+                    cur[i][c] = f;
+                    --cnt[i][c];
+                }
+                --rem[i];
+            }
+            // rows already done, and dummy slots: zero rows of free classes
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                if (fixed[i] || (placed >> i & 1u)) continue;
+                const int c = taken == (1u << M) - 1u ? 0 : __builtin_ctz(~taken);
+                taken |= 1u << c;
+                put(i, m, zero_row(c), 0.f);
+            }
+        }
+    }
+    // entries past L up to the end of the last chunk (never read)
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        if (fixed[i]) continue;
+        for (int m = d.L; m < d.words; ++m) put(i, m, d.n * d.stride, 0.f);
+    }
+}
+
+__global__ __launch_bounds__(256) void res_layout_kernel(const int32_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ col_idx,
+                                                        const float* __restrict__ weight,
+                                                        const float* __restrict__ invd,
+                                                        const int64_t* __restrict__ node_off, int32_t n_single,
+                                                        ResSlot* __restrict__ slots, int32_t* __restrict__ arcs,
+                                                        float* __restrict__ warcs) {
     constexpr int kMaxRows = 4096;
     __shared__ uint32_t key[kMaxRows];
+    __shared__ int64_t goff[kResMaxGroups + 1];
+    __shared__ int32_t ghalves[kResMaxGroups];
     const int g = blockIdx.x;
     const int64_t base = node_off ? node_off[g] : 0;
     const int n = node_off ? (int)(node_off[g + 1] - base) : n_single;
-    if (n <= 0 || n > kMaxRows) return;  // larger graphs never use the resident tile
+    const int cols = n > 0 ? res_cols_for(n) : 0;
+    if (cols == 0) return;  // larger graphs never use the resident tile
+    const int GW = 256 / cols;                            // group size, Res<cols>::RPW
+    const int M = cols == 16 ? 4 : (cols == 32 ? 2 : 1);  // bank classes = rows per LDS pass
+    const int stride = cols * 4;                          // LDS bytes per row
+    TileTask tb;
+    res_graph_bases(base, row_ptr[base], row_ptr[base + n], g, n, tb);
+
     int P = 1;
     while (P < n) P <<= 1;
     for (int i = threadIdx.x; i < P; i += 256) {
@@ -68,95 +246,82 @@ __global__ __launch_bounds__(256) void row_table_kernel(const int32_t* __restric
             __syncthreads();
         }
     }
-    for (int p = threadIdx.x; p < n; p += 256) {
-        const int v = (int)(key[p] & 4095u);
-        const int64_t gv = base + v;
-        const int rs = row_ptr[gv] + kArcRowPad * (int)gv;
-        table[base + p] = RowEnt{rs, rs + (row_ptr[gv + 1] - row_ptr[gv]), v, 0};
+    const int ng = (n + GW - 1) / GW;
+    for (int gi = threadIdx.x; gi < ng; gi += 256) {
+        int dmax = 1;
+        for (int r = 0; r < GW; ++r) {
+            const int p = gi * GW + r;
+            if (p < n) {
+                const int64_t gv = base + (int)(key[p] & 4095u);
+                dmax = max(dmax, row_ptr[gv + 1] - row_ptr[gv]);
+            }
+        }
+        const int h = (int)(((int64_t)dmax + 7) / 8);
+        ghalves[gi] = h;
+        goff[gi + 1] = (int64_t)((h + 1) / 2) * 16 * GW;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        goff[0] = 0;
+        for (int gi = 0; gi < ng; ++gi) goff[gi + 1] += goff[gi];
+    }
+    __syncthreads();
+    const bool over = goff[ng] > (int64_t)tb.cwords;
+    // slot table
+    for (int p = threadIdx.x; p < ng * GW; p += 256) {
+        const int gi = p / GW;
+        const int r = p - gi * GW;
+        const int h = over ? 1 : ghalves[gi];
+        const int64_t o = over ? (int64_t)gi * 16 * GW + 16 * r : goff[gi] + 16 * r;
+        int v = n;
+        float iv = 0.f;
+        if (p < n) {
+            v = (int)(key[p] & 4095u);
+            iv = over ? __int_as_float(0x7fc00000) : invd[base + v];
+        }
+        slots[tb.tbase + p] = ResSlot{(int32_t)o, h, v, iv};
+    }
+    // arcs: one thread per set of M rows of a group whose reads share LDS
+    // cycles (4 sets per group)
+    for (int t = threadIdx.x; t < ng * 4; t += 256) {
+        const int gi = t >> 2;
+        ResDealSet d;
+        d.L = over ? 16 : ghalves[gi] * 8;
+        d.words = over ? 16 : (ghalves[gi] + 1) / 2 * 16;
+        d.ca = arcs + tb.cbase + (over ? (int64_t)gi * 16 * GW : goff[gi]);
+        d.wa = warcs ? warcs + tb.cbase + (over ? (int64_t)gi * 16 * GW : goff[gi]) : nullptr;
+        d.GW = GW;
+        d.n = n;
+        d.stride = stride;
+        d.base = base;
+        d.over = over;
+        d.row_ptr = row_ptr;
+        d.col_idx = col_idx;
+        d.weight = weight;
+        int rr[4];
+        res_conflict_set(M, t & 3, rr);
+        int v[4];
+        for (int i = 0; i < 4; ++i) {
+            const int p = gi * GW + rr[i];
+            v[i] = (i < M && p < n) ? (int)(key[p] & 4095u) : -1;
+        }
+        if (M == 4) res_deal_set<4>(d, rr, v);
+        else if (M == 2) res_deal_set<2>(d, rr, v);
+        else res_deal_set<1>(d, rr, v);
     }
 }
 
-// Copy of the arcs for the resident tile, one thread per row slot of all
-// graphs, with each row's arcs dealt by LDS bank class.  In the tile, the four
-// quads of a 16-lane LDS pass read the rows of four consecutive slot
-// positions, arc position m of each at the same instruction, and a row u of a
-// 16- (32-) column tile starts in bank group u mod 4 (u mod 2).  Position m of
-// the row in slot p therefore takes an arc of class (m + p) mod 4 (mod 2)
-// while that class lasts, so the four reads of a pass fall in different bank
-// groups.  Only the order of each row's arcs changes (and with it the order of
-// the FP32 sum).  The copy holds each arc's LDS byte offset in the tile,
-// (u - first node) * 4 COLS, not its node id, and each row with arcs is
-// padded with the offset of the tile's zero row to at least 16 arcs and to a
-// multiple of 8, so the tile's chunks (a full 16-arc chunk first, then full
-// chunks and a last one of 16 or 8) need no bound checks.
-__global__ __launch_bounds__(256) void bank_order_kernel(const int32_t* __restrict__ col_idx,
-                                                        const float* __restrict__ weight,
-                                                        const int64_t* __restrict__ node_off, int32_t n_graphs,
-                                                        int64_t n_slots, const RowEnt* __restrict__ table,
-                                                        int32_t* __restrict__ col_out, float* __restrict__ w_out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_slots) return;
-    int g = 0;
-    if (node_off) {  // graph of slot i: largest g with node_off[g] <= i
-        int lo = 0, hi = n_graphs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (node_off[mid] <= i) lo = mid; else hi = mid - 1;
-        }
-        g = lo;
-    }
-    const int64_t base = node_off ? node_off[g] : 0;
-    const int n = node_off ? (int)(node_off[g + 1] - base) : (int)n_slots;
-    const int p = (int)(i - base);
-    const int cols = res_cols_for(n);
-    const int M = cols == 16 ? 4 : (cols == 32 ? 2 : 1);  // bank classes
-    const int stride = (cols > 0 ? cols : 16) * 4;        // LDS bytes per row
-    const RowEnt r = table[i];
-    const int shift = kArcRowPad * (int)(base + r.v);  // copy position - CSR position
-    const int rs = r.rs - shift, re = r.re - shift;
-    const int deg = re - rs;
-    const int pad_end = r.rs + (deg == 0 ? 0 : max(16, (deg + 7) / 8 * 8));
-    for (int m = r.re; m < pad_end; ++m) {
-        col_out[m] = n * stride;
-        if (w_out) w_out[m] = 0.f;
-    }
-    if (M == 1) {
-        for (int e = rs; e < re; ++e) {
-            col_out[e + shift] = (int)(col_idx[e] - base) * stride;
-            if (w_out) w_out[e + shift] = weight[e];
-        }
-        return;
-    }
-    // next[c]: next arc of class c in the original order (re when none)
-    int next[4];
-    for (int c = 0; c < 4; ++c) {
-        int e = rs;
-        while (e < re && (int)((col_idx[e] - base) & (M - 1)) != c) ++e;
-        next[c] = c < M ? e : re;
-    }
-    for (int m = rs; m < re; ++m) {
-        int c = (m - rs + p) & (M - 1);
-        for (int t = 0; t < M && next[c] >= re; ++t) c = (c + 1) & (M - 1);
-        const int e = next[c];
-        col_out[m + shift] = (int)(col_idx[e] - base) * stride;
-        if (w_out) w_out[m + shift] = weight[e];
-        int f = e + 1;
-        while (f < re && (int)((col_idx[f] - base) & (M - 1)) != c) ++f;
-        next[c] = f;
-    }
-}
 
-void launch_row_table(const int32_t* row_ptr, const int32_t* col_idx, const float* weight,
-                      const int64_t* node_off, int32_t n_single, int32_t blocks, int64_t n_slots, RowEnt* table,
-                      int32_t* col_out, float* w_out, hipStream_t s) {
-    hipLaunchKernelGGL(row_table_kernel, dim3(blocks), dim3(256), 0, s, row_ptr, node_off, n_single, table);
-    hipLaunchKernelGGL(bank_order_kernel, dim3((unsigned)((n_slots + 255) / 256)), dim3(256), 0, s, col_idx, weight,
-                       node_off, blocks, n_slots, table, col_out, w_out);
+void launch_res_layout(const int32_t* row_ptr, const int32_t* col_idx, const float* weight, const float* invd,
+                       const int64_t* node_off, int32_t n_single, int32_t blocks, ResSlot* slots, int32_t* arcs,
+                       float* warcs, hipStream_t s) {
+    hipLaunchKernelGGL(res_layout_kernel, dim3(blocks), dim3(256), 0, s, row_ptr, col_idx, weight, invd, node_off,
+                       n_single, slots, arcs, warcs);
 }
 
 template <int COLS, bool WEIGHTED>
-__global__ __launch_bounds__(kResThreads) void ppr_resident_kernel(ResArgs a, int32_t n, int32_t n_src,
-                                                                 int32_t n_tgt) {
+__global__ __launch_bounds__(kResThreads) void ppr_resident_kernel(ResArgs a, int32_t n, int64_t nnz,
+                                                                 int32_t n_src, int32_t n_tgt) {
     __shared__ ResLds L;
     TileTask t;
     t.n = n;
@@ -166,6 +331,7 @@ __global__ __launch_bounds__(kResThreads) void ppr_resident_kernel(ResArgs a, in
     t.base = 0;
     t.out_off = 0;
     t.ld = n_tgt;
+    res_graph_bases(0, 0, nnz, 0, n, t);
     res_tile<COLS, WEIGHTED>(t, a, L);
 }
 
@@ -176,12 +342,14 @@ void launch_degree(const int32_t* row_ptr, const float* weight, int64_t n, float
 }
 
 template <int COLS>
-static void launch_resident(bool weighted, const ResArgs& a, int n, int n_src, int n_tgt, hipStream_t s) {
+static void launch_resident(bool weighted, const ResArgs& a, int n, int64_t nnz, int n_src, int n_tgt,
+                            hipStream_t s) {
     dim3 grid((n_src + COLS - 1) / COLS);
     if (weighted)
-        hipLaunchKernelGGL((ppr_resident_kernel<COLS, true>), grid, dim3(kResThreads), 0, s, a, n, n_src, n_tgt);
+        hipLaunchKernelGGL((ppr_resident_kernel<COLS, true>), grid, dim3(kResThreads), 0, s, a, n, nnz, n_src, n_tgt);
     else
-        hipLaunchKernelGGL((ppr_resident_kernel<COLS, false>), grid, dim3(kResThreads), 0, s, a, n, n_src, n_tgt);
+        hipLaunchKernelGGL((ppr_resident_kernel<COLS, false>), grid, dim3(kResThreads), 0, s, a, n, nnz, n_src,
+                           n_tgt);
 }
 
 ppr_status validate_csr(const ppr_csr* g) {
@@ -201,14 +369,12 @@ void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int3
                  double* resid, const PprWs& w, hipStream_t s) {
     const int n = g->n;
     if (use_resident(n)) {
-        launch_row_table(g->row_ptr, g->col_idx, g->weight, nullptr, n, 1, n, w.rows, w.col_r,
-                         g->weight ? w.w_r : nullptr, s);
+        launch_res_layout(g->row_ptr, g->col_idx, g->weight, invd, nullptr, n, 1, w.slots, w.col_r,
+                          g->weight ? w.w_r : nullptr, s);
         ResArgs a;
-        a.rows = w.rows;
-        a.row_ptr = g->row_ptr;
-        a.col_idx = w.col_r;
-        a.weight = g->weight ? w.w_r : nullptr;
-        a.invd = invd;
+        a.slots = w.slots;
+        a.arcs = w.col_r;
+        a.warcs = g->weight ? w.w_r : nullptr;
         a.deg = deg;
         a.src = src;
         a.tgt = tgt;
@@ -219,9 +385,9 @@ void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int3
         a.resid = resid;
         const bool wt = g->weight != nullptr;
         switch (res_cols_for(n)) {
-            case 64: launch_resident<64>(wt, a, n, n_src, n_tgt, s); break;
-            case 32: launch_resident<32>(wt, a, n, n_src, n_tgt, s); break;
-            default: launch_resident<16>(wt, a, n, n_src, n_tgt, s); break;
+            case 64: launch_resident<64>(wt, a, n, g->nnz, n_src, n_tgt, s); break;
+            case 32: launch_resident<32>(wt, a, n, g->nnz, n_src, n_tgt, s); break;
+            default: launch_resident<16>(wt, a, n, g->nnz, n_src, n_tgt, s); break;
         }
     } else if (mid_cols_for(n) != 0) {
         mid_forward(g, src, n_src, tgt, n_tgt, alpha, T, ppr_out, dppr_out, deg, invd, resid, w.mid, s);

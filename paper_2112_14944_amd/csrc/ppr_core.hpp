@@ -21,46 +21,78 @@ namespace pprviz {
 // 1024 threads (16 waves, 4 per SIMD) leave each wave 128 VGPRs.
 constexpr int kResThreads = 1024;
 constexpr int kResWaves = kResThreads / kWave;
-constexpr int kArcPad = 16;  // padding entries after the tile's arc array (chunk loads read ahead)
-constexpr int kArcRowPad = 16;  // room per row in the tile's arc copy for padding the row
-constexpr int kResMaxK = 9;  // rows per lane (4 columns each) held in registers across a step
+constexpr int kResMaxK = 9;  // passes (row groups per wave) held in registers across a step
 
 // Tile geometry.  Lanes work in quads: a quad owns 16 columns of one row, each
 // lane 4 consecutive columns read with one 16-byte LDS load per arc, and the
 // quad's arcs are broadcast inside the quad with DPP quad_perm.  A row of a
-// COLS-wide tile takes COLS/16 quads.
+// COLS-wide tile takes COLS/16 quads; a wave takes RPW rows side by side (a
+// group) per pass.
 template <int COLS>
 struct Res {
     static constexpr int QPR = COLS / 16;                  // quads per row
-    static constexpr int RPW = 16 / QPR;                   // rows per wave per pass
+    static constexpr int RPW = 16 / QPR;                   // rows per wave per pass (group size)
     static constexpr int RPP = kResWaves * RPW;            // rows per block pass
     static constexpr int NMAX = RPP * kResMaxK;            // largest graph for this tile width
     static constexpr int STRIDE = COLS * 4;                // bytes per LDS row
 };
 
-// LDS floats for one resident tile: n rows plus one zero row, times COLS; the
-// maximum over the three tile widths (577*64, 1153*32, 2305*16).
+// LDS floats for one resident tile: n rows plus one zero row per LDS bank
+// class (4, 2, 1 for 16, 32, 64 columns: 64 floats in every case), times
+// COLS; the maximum over the three tile widths (577*64, 1154*32, 2308*16).
+constexpr int kResZeroFloats = 64;
 constexpr int kResLdsFloats = 36928;
-static_assert((Res<64>::NMAX + 1) * 64 <= kResLdsFloats, "lds");
-static_assert((Res<32>::NMAX + 1) * 32 <= kResLdsFloats, "lds");
-static_assert((Res<16>::NMAX + 1) * 16 <= kResLdsFloats, "lds");
+static_assert(Res<64>::NMAX * 64 + kResZeroFloats <= kResLdsFloats, "lds");
+static_assert(Res<32>::NMAX * 32 + kResZeroFloats <= kResLdsFloats, "lds");
+static_assert(Res<16>::NMAX * 16 + kResZeroFloats <= kResLdsFloats, "lds");
 
 __host__ __device__ inline int res_cols_for(int n) {
     return n <= Res<64>::NMAX ? 64 : (n <= Res<32>::NMAX ? 32 : (n <= Res<16>::NMAX ? 16 : 0));
 }
 
-// One source tile of one graph.
-struct TileTask {
-    int32_t n;        // node count of the graph
-    int32_t s0;       // first source index of the tile
-    int32_t ncols;    // sources in the tile (<= COLS)
-    int32_t n_tgt;    // output columns
-    int64_t base;     // global id of the graph's node 0
-    int64_t out_off;  // offset of output row 0
-    int64_t ld;       // output leading dimension
+// Group layout of the resident tile (res_layout_kernel).  The slots of a
+// graph are its rows in degree order, longest first; slots g*RPW .. g*RPW +
+// RPW - 1 form group g, the rows one wave sums side by side in one pass.
+// Every row of a group is padded (with the tile's zero row) to the length of
+// the group's longest row, rounded up to 8 arcs, so all lanes of a pass run
+// the same number of 16-arc chunks (the last one half full when the count of
+// 8-arc halves is odd) under scalar control.  The group's arcs are stored
+// chunk-major: entry j of chunk c of the group's row r sits at
+//     off(g) + 16 RPW c + 16 r + j,
+// so a lane's 4 arcs of a chunk are one 16-byte load at a lane-constant
+// offset plus a scalar one.  A row without arcs gets one arc to itself (its
+// own mass stays put, the self-loop convention).  Padding reads one of the
+// tile's zero rows (one per LDS bank class, rows n .. n + 64/COLS - 1).
+// Slots past the last row (the end of the last group) are dummies: every arc
+// is a zero row and the row they write back is zero row n itself, with
+// zeros.
+constexpr int kResTabPad = 16;        // slot-table entries per graph beyond its n rows
+constexpr int kResArcPerNode = 32;    // arc-copy entries per node beyond its arcs
+constexpr int kResArcPerGraph = 256;  // and per graph
+constexpr int kResMaxGroups = Res<16>::NMAX / Res<16>::RPW;
+static_assert(Res<32>::NMAX / Res<32>::RPW == kResMaxGroups && Res<64>::NMAX / Res<64>::RPW == kResMaxGroups,
+              "groups");
+
+// Arc-copy entries reserved for a graph of n nodes and nnz arcs.  With the
+// rows sorted longest first, group g >= 1 is padded to a length no longer
+// than any row of group g - 1, so the padded groups hold at most
+// RPW * dmax + nnz + n entries (the n for the self arcs), plus at most 15 per
+// row for rounding to whole chunks: below nnz + 32 n + 256 whenever dmax <= n
+// (no repeated arcs).  A graph that needs more (repeated arcs) gets a
+// minimal layout and NaN scales, so its outputs are NaN.
+__host__ __device__ inline int64_t res_arc_words(int64_t nnz, int64_t n) {
+    return nnz + kResArcPerNode * n + kResArcPerGraph;
+}
+
+// Slot-table entry of the resident tile.
+struct __attribute__((aligned(16))) ResSlot {
+    int32_t off;     // arc-copy entry of the slot's row, chunk 0, relative to the graph's copy
+    int32_t halves;  // 8-arc halves of every row of the slot's group (>= 1)
+    int32_t v;       // row id (local to its graph); n for a dummy slot
+    float invd;      // 1/d of the row (0 for a dummy slot)
 };
 
-// Row table entry: a row of the resident tile's slot order.
+// Row entry of the mid-size and streaming kernels' row orders.
 struct __attribute__((aligned(16))) RowEnt {
     int32_t rs;   // first arc
     int32_t re;   // one past the last arc
@@ -77,12 +109,33 @@ __device__ __forceinline__ RowEnt load_row(gcptr<RowEnt> p, int64_t i) {
     return e;
 }
 
+// One source tile of one graph.
+struct TileTask {
+    int32_t n;        // node count of the graph
+    int32_t s0;       // first source index of the tile
+    int32_t ncols;    // sources in the tile (<= COLS)
+    int32_t n_tgt;    // output columns
+    int64_t base;     // global id of the graph's node 0
+    int64_t out_off;  // offset of output row 0
+    int64_t ld;       // output leading dimension
+    int64_t tbase;    // first slot-table entry of the graph
+    int64_t cbase;    // first arc-copy entry of the graph
+    int32_t cwords;   // arc-copy entries of the graph (res_arc_words)
+};
+
+// Where graph g's slot table and arc copy start, for a graph whose nodes start
+// at global id `base` and whose arcs start at CSR position e0.
+__host__ __device__ inline void res_graph_bases(int64_t base, int64_t e0, int64_t e1, int64_t g, int32_t n,
+                                                TileTask& t) {
+    t.tbase = base + kResTabPad * g;
+    t.cbase = e0 + kResArcPerNode * base + kResArcPerGraph * g;
+    t.cwords = (int32_t)res_arc_words(e1 - e0, n);
+}
+
 struct ResArgs {
-    const RowEnt* rows;      // per graph, rows in slot order (row_table_kernel)
-    const int32_t* row_ptr;  // global CSR row pointers
-    const int32_t* col_idx;  // arc copy (bank_order_kernel): LDS byte offset of the neighbour's row, rows padded
-    const float* weight;     // arc weights, or nullptr
-    const float* invd;       // per global node: 1/d, or 1 for a node without arcs
+    const ResSlot* slots;    // per graph: slot table in group layout (res_layout_kernel)
+    const int32_t* arcs;     // arc copy in group layout: LDS byte offset of each arc's neighbour row
+    const float* warcs;      // arc weights in the same layout, or nullptr
     const float* deg;        // per global node: weighted degree d
     const int32_t* src;      // source local ids by source index, or nullptr (source i = node i)
     const int32_t* tgt;      // target local ids, or nullptr (targets = nodes 0..n_tgt-1)
@@ -107,47 +160,9 @@ __device__ __forceinline__ float4 lds_load4(const float* lds, int byte_off) {
     return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(lds) + byte_off);
 }
 
-// One chunk of 16 arcs (NH = 2 halves) or 8 arcs (NH = 1) of a quad's row:
-// arc 4L + W sits in lane L, word W (a0..a3 hold LDS byte offsets of the
-// neighbours' rows, the zero row past the row's end), so the arcs are summed
-// in row order.  Eight 16-byte reads are issued before their adds.
-template <bool WEIGHTED, int NH>
-__device__ __forceinline__ void gather_chunk(const float* __restrict__ lds, int a0, int a1, int a2, int a3,
-                                             float w0, float w1, float w2, float w3, int cbyte, float4& acc) {
-#define PPRVIZ_RD(M, A) y[(M) & 7] = lds_load4(lds, quad_bcast<(M) / 4>(A) + cbyte);
-#define PPRVIZ_ACC(M, W)                                          \
-    if (WEIGHTED) {                                               \
-        const float ww = quad_bcast<(M) / 4>(W);                  \
-        acc.x = fmaf(ww, y[(M) & 7].x, acc.x);                    \
-        acc.y = fmaf(ww, y[(M) & 7].y, acc.y);                    \
-        acc.z = fmaf(ww, y[(M) & 7].z, acc.z);                    \
-        acc.w = fmaf(ww, y[(M) & 7].w, acc.w);                    \
-    } else {                                                      \
-        acc.x += y[(M) & 7].x;                                    \
-        acc.y += y[(M) & 7].y;                                    \
-        acc.z += y[(M) & 7].z;                                    \
-        acc.w += y[(M) & 7].w;                                    \
-    }
-    float4 y[8];
-    PPRVIZ_RD(0, a0) PPRVIZ_RD(1, a1) PPRVIZ_RD(2, a2) PPRVIZ_RD(3, a3)
-    PPRVIZ_RD(4, a0) PPRVIZ_RD(5, a1) PPRVIZ_RD(6, a2) PPRVIZ_RD(7, a3)
-    __builtin_amdgcn_sched_barrier(0);
-    PPRVIZ_ACC(0, w0) PPRVIZ_ACC(1, w1) PPRVIZ_ACC(2, w2) PPRVIZ_ACC(3, w3)
-    PPRVIZ_ACC(4, w0) PPRVIZ_ACC(5, w1) PPRVIZ_ACC(6, w2) PPRVIZ_ACC(7, w3)
-    if (NH == 1) return;
-    __builtin_amdgcn_sched_barrier(0);
-    PPRVIZ_RD(8, a0) PPRVIZ_RD(9, a1) PPRVIZ_RD(10, a2) PPRVIZ_RD(11, a3)
-    PPRVIZ_RD(12, a0) PPRVIZ_RD(13, a1) PPRVIZ_RD(14, a2) PPRVIZ_RD(15, a3)
-    __builtin_amdgcn_sched_barrier(0);
-    PPRVIZ_ACC(8, w0) PPRVIZ_ACC(9, w1) PPRVIZ_ACC(10, w2) PPRVIZ_ACC(11, w3)
-    PPRVIZ_ACC(12, w0) PPRVIZ_ACC(13, w1) PPRVIZ_ACC(14, w2) PPRVIZ_ACC(15, w3)
-#undef PPRVIZ_RD
-#undef PPRVIZ_ACC
-}
-
 // Keeps a value opaque to the optimizer, so that per-row loads and addresses
-// are recomputed inside each step instead of being hoisted out of the step
-// loop (where 18 rows' worth of them would no longer fit in registers).
+// are recomputed inside a loop instead of being hoisted out of it (where many
+// rows' worth of them would no longer fit in registers).
 __device__ __forceinline__ int opaque(int v) {
     asm volatile("" : "+v"(v));
     return v;
@@ -164,62 +179,116 @@ __device__ __forceinline__ int64_t opaque_s(int64_t v) {
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
 }
 
-// LDS of one resident tile: the iterate Y (n rows of COLS floats and a zero
-// row) followed by the n per-node factors (1-alpha)/d.
+// A pointer or count the caller knows to be wave-uniform, moved to scalar
+// registers (a buffer resource built from values in vector registers is
+// otherwise taken lane by lane, one load per distinct value).
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T*)(((uint64_t)hi << 32) | lo);
+}
+
+// 16-byte load through a buffer resource (offsets in bytes; soff must be
+// wave-uniform).
+__device__ __forceinline__ int4 buf_load_i4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+    return make_int4((int)v[0], (int)v[1], (int)v[2], (int)v[3]);
+}
+// A group's arc start and length: its first slot entry, the same for all
+// lanes.
+__device__ __forceinline__ int2 grp_load(__amdgpu_buffer_rsrc_t r, uint32_t soff) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, 0, (int)soff, 0);
+    return make_int2((int)v[0], (int)v[1]);
+}
+__device__ __forceinline__ float4 buf_load_f4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+    return make_float4(__int_as_float(v[0]), __int_as_float(v[1]), __int_as_float(v[2]), __int_as_float(v[3]));
+}
+
+// One chunk of 16 arcs of a quad's row (8 when `half`, a wave-uniform flag):
+// arc 4L + W sits in lane L, word W (a.x..a.w hold LDS byte offsets of the
+// neighbours' rows, the zero row past the row's end), so the arcs are summed
+// in row order.  Eight 16-byte reads are issued before their adds.
+template <bool WEIGHTED>
+__device__ __forceinline__ void gather_chunk(const float* __restrict__ lds, int4 a, float4 w, int cbyte, bool half,
+                                             float4& acc) {
+#define PPRVIZ_RD(M, A) y[(M) & 7] = lds_load4(lds, quad_bcast<(M) / 4>(A) + cbyte);
+#define PPRVIZ_ACC(M, W)                                          \
+    if (WEIGHTED) {                                               \
+        const float ww = quad_bcast<(M) / 4>(W);                  \
+        acc.x = fmaf(ww, y[(M) & 7].x, acc.x);                    \
+        acc.y = fmaf(ww, y[(M) & 7].y, acc.y);                    \
+        acc.z = fmaf(ww, y[(M) & 7].z, acc.z);                    \
+        acc.w = fmaf(ww, y[(M) & 7].w, acc.w);                    \
+    } else {                                                      \
+        acc.x += y[(M) & 7].x;                                    \
+        acc.y += y[(M) & 7].y;                                    \
+        acc.z += y[(M) & 7].z;                                    \
+        acc.w += y[(M) & 7].w;                                    \
+    }
+    float4 y[8];
+    PPRVIZ_RD(0, a.x) PPRVIZ_RD(1, a.y) PPRVIZ_RD(2, a.z) PPRVIZ_RD(3, a.w)
+    PPRVIZ_RD(4, a.x) PPRVIZ_RD(5, a.y) PPRVIZ_RD(6, a.z) PPRVIZ_RD(7, a.w)
+    __builtin_amdgcn_sched_barrier(0);
+    PPRVIZ_ACC(0, w.x) PPRVIZ_ACC(1, w.y) PPRVIZ_ACC(2, w.z) PPRVIZ_ACC(3, w.w)
+    PPRVIZ_ACC(4, w.x) PPRVIZ_ACC(5, w.y) PPRVIZ_ACC(6, w.z) PPRVIZ_ACC(7, w.w)
+    if (half) return;
+    __builtin_amdgcn_sched_barrier(0);
+    PPRVIZ_RD(8, a.x) PPRVIZ_RD(9, a.y) PPRVIZ_RD(10, a.z) PPRVIZ_RD(11, a.w)
+    PPRVIZ_RD(12, a.x) PPRVIZ_RD(13, a.y) PPRVIZ_RD(14, a.z) PPRVIZ_RD(15, a.w)
+    __builtin_amdgcn_sched_barrier(0);
+    PPRVIZ_ACC(8, w.x) PPRVIZ_ACC(9, w.y) PPRVIZ_ACC(10, w.z) PPRVIZ_ACC(11, w.w)
+    PPRVIZ_ACC(12, w.x) PPRVIZ_ACC(13, w.y) PPRVIZ_ACC(14, w.z) PPRVIZ_ACC(15, w.w)
+#undef PPRVIZ_RD
+#undef PPRVIZ_ACC
+}
+
+// LDS of one resident tile: the iterate Y (n rows of COLS floats and the zero
+// rows).
 struct ResLds {
     float y[kResLdsFloats];
-    float scale[Res<16>::NMAX];
 };
 
-// Loads one 16-arc chunk of a quad's row (arcs e0 + 4i + q for i = 0..3).
-// Rows of the arc copy are padded with the zero row's offset to at least 16
-// arcs and to a multiple of 8, and a later chunk with at most 8 arcs left
-// uses only lanes 0 and 1, so every arc the gather uses is a real arc or the
-// zero row: no bound checks.
-template <bool WEIGHTED>
-__device__ __forceinline__ void load_chunk(gcptr<int32_t> pc, gcptr<float> pw, int e0, int q, int& r0, int& r1,
-                                           int& r2, int& r3, float& w0, float& w1, float& w2, float& w3) {
-    // lane q takes the 4 consecutive arcs e0 + 4q .. e0 + 4q + 3; the arc
-    // array is padded by 16 entries, so the loads need no guard
-    const int e = e0 + 4 * q;
-    r0 = pc[e];
-    r1 = pc[e + 1];
-    r2 = pc[e + 2];
-    r3 = pc[e + 3];
-    if (WEIGHTED) {
-        w0 = pw[e];
-        w1 = pw[e + 1];
-        w2 = pw[e + 2];
-        w3 = pw[e + 3];
-    }
-}
+constexpr int kBufFlags = 0x00020000;  // buffer resource word 3: 32-bit data, no swizzle
 
 // All T pushes for one source tile with the tile's iterate resident in LDS.
 // Each lane keeps its rows' new values (4 columns per row) in registers
-// between the two barriers of a step.
+// between the two barriers of a step.  Pass k of wave w sums group
+// w + 16 k of the slot table; all control flow inside a step is wave-uniform.
 template <int COLS, bool WEIGHTED>
 __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, ResLds& L) {
     constexpr int QPR = Res<COLS>::QPR;
     constexpr int RPW = Res<COLS>::RPW;
-    constexpr int RPP = Res<COLS>::RPP;
     constexpr int STRIDE = Res<COLS>::STRIDE;
+    constexpr uint32_t kChunkBytes = 64u * RPW;  // one 16-arc chunk of a group
+    constexpr uint32_t kGroupBytes = 16u * RPW;  // one group's slot entries
     float* __restrict__ lds = L.y;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
-    const int wave = tid / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int quad = lane >> 2;
     const int q = lane & 3;
-    const int rsub = quad / QPR;                 // row slot of the quad in the wave
+    const int rsub = quad / QPR;                 // row of the quad in its group
     const int col0 = (quad % QPR) * 16 + q * 4;  // first of the lane's 4 columns
     const int cbyte = col0 * 4;
-    const int n = t.n;
-    const int64_t base = t.base;
+    const int n = __builtin_amdgcn_readfirstlane(t.n);
+    const int ngroups = (n + RPW - 1) / RPW;
+    const int cbytes = __builtin_amdgcn_readfirstlane(t.cwords) * 4;
     const float alpha = a.alpha;
     const float oma = 1.0f - alpha;
-    const gcptr<int32_t> rp = as_global(a.row_ptr);
-    const gcptr<int32_t> pc = as_global(a.col_idx);
-    const gcptr<float> pw = as_global(a.weight);
     const gcptr<int32_t> srcp = as_global(a.src);
+    const __amdgpu_buffer_rsrc_t tab = __builtin_amdgcn_make_buffer_rsrc(
+        uniform_ptr(const_cast<ResSlot*>(a.slots + t.tbase)), 0, ngroups * (int)kGroupBytes, kBufFlags);
+    const __amdgpu_buffer_rsrc_t arc =
+        __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(const_cast<int32_t*>(a.arcs + t.cbase)), 0, cbytes, kBufFlags);
+    __amdgpu_buffer_rsrc_t warc = arc;
+    if (WEIGHTED)
+        warc = __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(const_cast<float*>(a.warcs + t.cbase)), 0, cbytes,
+                                                 kBufFlags);
+    const uint32_t tvoff = (uint32_t)rsub * 16u;                // the lane's slot entry within its group
+    const uint32_t lane_arc = (uint32_t)rsub * 64u + q * 16u;  // the lane's 4 arcs within a chunk
 
     // local source node of each of the lane's 4 columns (-1 outside the tile)
     int msrc[4];
@@ -229,100 +298,119 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
         msrc[i] = c < t.ncols ? (a.src ? srcp[t.s0 + c] : t.s0 + c) : -1;
     }
 
-    for (int i = tid; i < (n + 1) * COLS; i += kResThreads) lds[i] = 0.f;
-    for (int i = tid; i < n; i += kResThreads) L.scale[i] = oma * as_global(a.invd)[base + i];
-    __syncthreads();
-    if (tid < t.ncols && a.T >= 2) {
-        int s = a.src ? srcp[t.s0 + tid] : t.s0 + tid;
-        lds[s * COLS + tid] = alpha * L.scale[s];
-    }
-    __syncthreads();
-
+    // Per pass: the LDS byte address the row's 4 columns are stored to, the
+    // row's scale (1 - alpha)/d, and which of the lane's columns have the
+    // row as their source (4 bits per pass).
+    int vaddr[kResMaxK];
+    float sc[kResMaxK];
     float4 xr[kResMaxK];
-    int vs[kResMaxK];  // row id of each slot
-    const int row0 = wave * RPW + rsub;  // slot of pass k is row0 + k * RPP
+    uint32_t sbits_lo = 0, sbits_hi = 0;
 #pragma unroll
     for (int k = 0; k < kResMaxK; ++k) {
-        const int slot = row0 + k * RPP;
-        const int v = slot < n ? as_global(a.rows)[base + slot].v : -1;
-        vs[k] = v;
-        const bool on = a.T >= 1;
-        xr[k] = make_float4(on && v == msrc[0] ? alpha : 0.f, on && v == msrc[1] ? alpha : 0.f,
-                            on && v == msrc[2] ? alpha : 0.f, on && v == msrc[3] ? alpha : 0.f);
+        vaddr[k] = n * STRIDE + cbyte;
+        sc[k] = 0.f;
+        xr[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if ((wave + kResWaves * k) * RPW < n) {
+            const int4 e = buf_load_i4(tab, tvoff, (uint32_t)(wave + kResWaves * k) * kGroupBytes);
+            vaddr[k] = e.z * STRIDE + cbyte;
+            sc[k] = oma * __int_as_float(e.w);
+            const uint32_t bits = (e.z == msrc[0] ? 1u : 0u) | (e.z == msrc[1] ? 2u : 0u) |
+                                  (e.z == msrc[2] ? 4u : 0u) | (e.z == msrc[3] ? 8u : 0u);
+            if (k < 8) sbits_lo |= bits << (4 * k); else sbits_hi |= bits << (4 * (k - 8));
+            if (a.T >= 1)
+                xr[k] = make_float4(bits & 1u ? alpha : 0.f, bits & 2u ? alpha : 0.f, bits & 4u ? alpha : 0.f,
+                                    bits & 8u ? alpha : 0.f);
+        }
     }
+    // Y_0 = scale * X_0: every row is written by the lanes of its slot; the
+    // zero rows are cleared (dummy slots write zeros into the first as well)
+    for (int i = tid; i < kResZeroFloats; i += kResThreads) lds[n * COLS + i] = 0.f;
+#pragma unroll
+    for (int k = 0; k < kResMaxK; ++k) {
+        if ((wave + kResWaves * k) * RPW < n)
+            *reinterpret_cast<float4*>(reinterpret_cast<char*>(lds) + vaddr[k]) =
+                make_float4(xr[k].x * sc[k], xr[k].y * sc[k], xr[k].z * sc[k], xr[k].w * sc[k]);
+    }
+    __syncthreads();
 
-    const gcptr<RowEnt> rows = as_global(a.rows);
     for (int it = 1; it < a.T; ++it) {
-        const int r0 = opaque(row0);
-        const int64_t b = opaque_s(base);
-        const int n = opaque_s32(t.n);
-        // Rows are visited in slot order (degree-sorted, so the rows that
-        // share a pass have similar length).  Row-level software pipeline:
-        // the first chunk of slot k+1 and the table entry of slot k+2 are
-        // loaded while slot k is summed.
-        RowEnt e1 = {0, 0, 0, 0}, e2 = {0, 0, 0, 0};
-        if (r0 < n) e1 = load_row(rows, b + r0);
-        if (r0 + RPP < n) e2 = load_row(rows, b + r0 + RPP);
-        int p0 = 0, p1 = 0, p2 = 0, p3 = 0;
-        float pw0 = 0.f, pw1 = 0.f, pw2 = 0.f, pw3 = 0.f;
-        load_chunk<WEIGHTED>(pc, pw, e1.rs, q, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
+        // Chunk-level software pipeline: the arcs of the next chunk (of this
+        // pass, else the first of the next pass) are loaded while the current
+        // chunk is summed, alternating between two register sets.  A lane's 4
+        // arcs of any chunk sit at the lane-constant offset lane_arc from the
+        // chunk's start, so every arc load takes a scalar offset: the group's
+        // start g4 (bytes) plus the chunk's.  A group's start and length are
+        // loaded two passes ahead of their use.
+        int4 A = make_int4(0, 0, 0, 0), B = A;
+        float4 WA = make_float4(0.f, 0.f, 0.f, 0.f), WB = WA;
+        int2 e1 = make_int2(0, 1);
+        uint32_t g4 = 0;
+        int h = 1;
+        if (wave * RPW < n) {
+            const int2 e0 = grp_load(tab, (uint32_t)wave * kGroupBytes);
+            if ((wave + kResWaves) * RPW < n) e1 = grp_load(tab, (uint32_t)(wave + kResWaves) * kGroupBytes);
+            g4 = (uint32_t)__builtin_amdgcn_readfirstlane(e0.x) * 4u;
+            h = __builtin_amdgcn_readfirstlane(e0.y);
+            A = buf_load_i4(arc, lane_arc, g4);
+            if (WEIGHTED) WA = buf_load_f4(warc, lane_arc, g4);
+        }
+        // the source bits are re-read each step, so that their tests stay in
+        // vector registers instead of being hoisted into scalar masks
+        const uint32_t sl = (uint32_t)opaque((int)sbits_lo);
+        const uint32_t sh = (uint32_t)opaque((int)sbits_hi);
 #pragma unroll
         for (int k = 0; k < kResMaxK; ++k) {
-            if (k * RPP < n) {
-                const int slot = r0 + k * RPP;
-                const int rs = e1.rs, re = e1.re, v = e1.v;
-                const int c0 = p0, c1 = p1, c2 = p2, c3 = p3;
-                const float cw0 = pw0, cw1 = pw1, cw2 = pw2, cw3 = pw3;
-                e1 = e2;
-                if (k + 1 < kResMaxK && slot + RPP < n)
-                    load_chunk<WEIGHTED>(pc, pw, e1.rs, q, p0, p1, p2, p3, pw0, pw1, pw2, pw3);
-                if (k + 2 < kResMaxK && slot + 2 * RPP < n) e2 = load_row(rows, b + slot + 2 * RPP);
-                if (slot < n) {
-                    vs[k] = v;
-                    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (rs == re) acc = lds_load4(lds, v * STRIDE + cbyte);
-                    if (rs < re) {
-                        gather_chunk<WEIGHTED, 2>(lds, c0, c1, c2, c3, cw0, cw1, cw2, cw3, cbyte, acc);
+            const int gk = wave + kResWaves * k;
+            if (gk * RPW < n) {
+                const bool nxt = k + 1 < kResMaxK && (gk + kResWaves) * RPW < n;
+                int2 e2 = make_int2(0, 1);
+                if (k + 2 < kResMaxK && (gk + 2 * kResWaves) * RPW < n)
+                    e2 = grp_load(tab, (uint32_t)(gk + 2 * kResWaves) * kGroupBytes);
+                // next pass's start (this pass's own when there is none: the
+                // last prefetch then reloads a chunk already read)
+                const uint32_t g4n = nxt ? (uint32_t)__builtin_amdgcn_readfirstlane(e1.x) * 4u : g4;
+                const int hn = __builtin_amdgcn_readfirstlane(e1.y);
+                const int nch = (h + 1) >> 1;
+                const bool odd = (h & 1) != 0;
+                float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+                // chunks in pairs: A holds chunk c, B chunk c + 1
+                for (int c = 0;; c += 2) {
+                    const bool has1 = c + 1 < nch;
+                    const uint32_t s1 = has1 ? g4 + (uint32_t)(c + 1) * kChunkBytes : g4n;
+                    B = buf_load_i4(arc, lane_arc, s1);
+                    if (WEIGHTED) WB = buf_load_f4(warc, lane_arc, s1);
+                    gather_chunk<WEIGHTED>(lds, A, WA, cbyte, !has1 && odd, acc);
+                    if (!has1) {
+                        A = B;  // the next pass's first chunk
+                        WA = WB;
+                        break;
                     }
-                    // further chunks of rows longer than 16 arcs; a tail of
-                    // at most 8 arcs takes a half chunk
-#pragma nounroll
-                    for (int e0 = rs + 16; e0 < re; e0 += 16) {
-                        int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
-                        float dw0 = 0.f, dw1 = 0.f, dw2 = 0.f, dw3 = 0.f;
-                        load_chunk<WEIGHTED>(pc, pw, e0, q, d0, d1, d2, d3, dw0, dw1, dw2, dw3);
-                        if (re - e0 > 8) {
-                            gather_chunk<WEIGHTED, 2>(lds, d0, d1, d2, d3, dw0, dw1, dw2, dw3, cbyte, acc);
-                        } else {
-                            gather_chunk<WEIGHTED, 1>(lds, d0, d1, d2, d3, dw0, dw1, dw2, dw3, cbyte, acc);
-                        }
-                    }
-                    acc.x += v == msrc[0] ? alpha : 0.f;
-                    acc.y += v == msrc[1] ? alpha : 0.f;
-                    acc.z += v == msrc[2] ? alpha : 0.f;
-                    acc.w += v == msrc[3] ? alpha : 0.f;
-                    xr[k] = acc;
+                    const bool has2 = c + 2 < nch;
+                    const uint32_t s2 = has2 ? g4 + (uint32_t)(c + 2) * kChunkBytes : g4n;
+                    A = buf_load_i4(arc, lane_arc, s2);
+                    if (WEIGHTED) WA = buf_load_f4(warc, lane_arc, s2);
+                    gather_chunk<WEIGHTED>(lds, B, WB, cbyte, !has2 && odd, acc);
+                    if (!has2) break;
                 }
+                const uint32_t sb = (k < 8 ? sl >> (4 * k) : sh >> (4 * (k - 8))) & 15u;
+                if (sb) {
+                    acc.x += (sb & 1u) ? alpha : 0.f;
+                    acc.y += (sb & 2u) ? alpha : 0.f;
+                    acc.z += (sb & 4u) ? alpha : 0.f;
+                    acc.w += (sb & 8u) ? alpha : 0.f;
+                }
+                xr[k] = acc;
+                g4 = g4n;
+                h = hn;
+                e1 = e2;
             }
         }
-        // the slots' scales (constant for the tile) are read before the
-        // barrier, all at once, instead of one LDS round trip per slot after it
-        float sc[kResMaxK];
-#pragma unroll
-        for (int k = 0; k < kResMaxK; ++k) sc[k] = L.scale[max(vs[k], 0)];
         __syncthreads();
-        const int r1 = opaque(row0);
-        const int n1 = opaque_s32(t.n);
 #pragma unroll
         for (int k = 0; k < kResMaxK; ++k) {
-            if (k * RPP < n1) {
-                const int slot = r1 + k * RPP;
-                if (slot < n1) {
-                    const int v = vs[k];
-                    *reinterpret_cast<float4*>(reinterpret_cast<char*>(lds) + v * STRIDE + cbyte) =
-                        make_float4(xr[k].x * sc[k], xr[k].y * sc[k], xr[k].z * sc[k], xr[k].w * sc[k]);
-                }
-            }
+            if ((wave + kResWaves * k) * RPW < n)
+                *reinterpret_cast<float4*>(reinterpret_cast<char*>(lds) + vaddr[k]) =
+                    make_float4(xr[k].x * sc[k], xr[k].y * sc[k], xr[k].z * sc[k], xr[k].w * sc[k]);
         }
         __syncthreads();
     }
@@ -330,19 +418,18 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
     // Epilogue.  FP64 residual 1 - sum_v pi_hat(s, v): per-column partial sums
     // go through the (no longer needed) iterate area; then the unscaled
     // iterate is written column-swizzled so that the transposed read below is
-    // conflict-free.
+    // conflict-free.  Dummy slots hold zeros and add nothing.
     double part[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < kResMaxK; ++k) {
-        const int slot = row0 + k * RPP;
-        if (k * RPP < n && slot < n) {
+        if ((wave + kResWaves * k) * RPW < n) {
             part[0] += (double)xr[k].x;
             part[1] += (double)xr[k].y;
             part[2] += (double)xr[k].z;
             part[3] += (double)xr[k].w;
         }
     }
-    // lanes holding the same columns: same (quad % QPR, q), other row slots
+    // lanes holding the same columns: same (quad % QPR, q), other rows
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -363,9 +450,8 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kResMaxK; ++k) {
-        const int slot = row0 + k * RPP;
-        if (k * RPP < n && slot < n) {
-            const int v = vs[k];
+        if ((wave + kResWaves * k) * RPW < n) {
+            const int v = (vaddr[k] - cbyte) / STRIDE;
             const int sw = v & (COLS - 1);
             lds[v * COLS + ((col0 + 0) ^ sw)] = xr[k].x;
             lds[v * COLS + ((col0 + 1) ^ sw)] = xr[k].y;
@@ -374,6 +460,7 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
         }
     }
     __syncthreads();
+    const int64_t base = t.base;
     if (a.ppr_out || a.dppr_out) {
         for (int ci = 0; ci < t.ncols; ++ci) {
             const int s_local = a.src ? srcp[t.s0 + ci] : t.s0 + ci;
@@ -390,11 +477,13 @@ __device__ __forceinline__ void res_tile(const TileTask& t, const ResArgs& a, Re
     __syncthreads();
 }
 
-// Slot order of the rows of each graph for the resident tile: rows sorted by
-// degree, longest first (ties by row id); one block per graph.  node_off ==
-// nullptr means a single graph of n_single nodes.
-__global__ void row_table_kernel(const int32_t* __restrict__ row_ptr, const int64_t* __restrict__ node_off,
-                                 int32_t n_single, RowEnt* __restrict__ table);
+// Slot table and arc copy of the resident tile in group layout (see above),
+// one block per graph; node_off == nullptr means a single graph of n_single
+// nodes.  Needs the inverse degrees.
+__global__ void res_layout_kernel(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                                  const float* __restrict__ weight, const float* __restrict__ invd,
+                                  const int64_t* __restrict__ node_off, int32_t n_single, ResSlot* __restrict__ slots,
+                                  int32_t* __restrict__ arcs, float* __restrict__ warcs);
 
 // Degree and inverse degree of every node (the d of Definition def:pprdist is
 // the out-degree; with weights, the sum of the node's arc weights).

@@ -162,6 +162,38 @@ def test_mid_repeated_arcs_flagged(ops):
     assert torch.isnan(ppr).all().item()
 
 
+def test_resident_repeated_arcs(ops):
+    # n = 300 (resident tile, groups of 4 rows): two rows of 2000 repeated arcs
+    # pad their group to 2000 arcs per row, which still fits the arc copy's
+    # reserved region; the walk is that of a two-node path, node 5 isolated.
+    # Each row sums its 2000 equal terms one after another in FP32 (relative
+    # error up to 2000 u per push, u = 2^-24), and an error made in one push
+    # decays by (1 - alpha) per push: at most 2000 u / alpha relative.
+    csr = _repeated_arc_csr(ops, 300, 2000)
+    ppr, _, T, resid = ops.ppr_matrix(csr, [0, 5], tol=1e-6, check_residual=True)
+    est, _, T_o, _, _ = oracle_ppr(synth.build_graph(2, [0], [1]), [0], T=T)
+    p = ppr.double().cpu().numpy()
+    rel = 2000 * 2.0 ** -24 / ALPHA
+    print(f"[resident repeated arcs] err {abs(p[0, 0] - est[0, 0]):.3e} {abs(p[0, 1] - est[0, 1]):.3e} "
+          f"bound {rel * est[0, 0]:.3e}", flush=True)
+    assert abs(p[0, 0] - est[0, 0]) <= rel * est[0, 0] and abs(p[0, 1] - est[0, 1]) <= rel * est[0, 1]
+    assert np.abs(p[0, 2:]).max() == 0.0
+    assert abs(p[1, 5] - (1 - (1 - ALPHA) ** T)) <= 1e-6
+    assert np.abs(resid - (1 - ALPHA) ** T).max() <= 2e-6 + rel
+
+
+def test_resident_repeated_arcs_flagged(ops):
+    # with 5000 repeated arcs per row the padded first group would exceed the
+    # reserved region: the layout reports it through NaN outputs
+    csr = _repeated_arc_csr(ops, 300, 5000)
+    from paper_2112_14944_amd._lib import PPR_ENONFINITE, PprvizError
+    with pytest.raises(PprvizError) as ei:
+        ops.ppr_matrix(csr, [0, 5], tol=1e-6, check_residual=True)
+    assert ei.value.status == PPR_ENONFINITE
+    ppr, _, _, _ = ops.ppr_matrix(csr, [0, 5], tol=1e-6)
+    assert torch.isnan(ppr).all().item()
+
+
 def test_degenerate_cases(ops):
     # single isolated node; two-node path (closed form 1/(2 - alpha)); T = 0; T = 1; no sources
     g1 = synth.build_graph(1, [], [])
