@@ -128,7 +128,7 @@ ppr_status ppr_matrix(const ppr_csr* g, const int32_t* src, int32_t n_src,
  * Limit: the workspace ppr_matrix_workspace(g, n_src, n_tgt) would ask for
  * must fit ppr_matrix_noalloc_max_scratch() bytes (8 MiB), else the call
  * returns PPR_EUNSUPPORTED before any launch.  That covers, for example, the
- * LDS-resident path (n <= 2304) up to about 2 million arcs unweighted.
+ * LDS-resident path (n <= 2304) up to about 1 million arcs unweighted.
  *
  * The scratch is one array per GPU, held from the first call on that GPU
  * until the process ends (its device address is looked up once per device).

@@ -443,6 +443,7 @@ __global__ void copy_kernel(const float* __restrict__ a, float* __restrict__ b, 
 struct BatchWs {
     ResSlot* slots;  // resident-tile slot tables (res_layout_kernel)
     int32_t* col_r;  // arc copies in group layout
+    int32_t* sorted_r;  // arcs grouped by LDS bank class (layout staging)
     float* deg;
     float* invd;
     float* inv;   // 1/Delta pool (zero diagonal)
@@ -460,6 +461,7 @@ static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     t.slots = c.template take<ResSlot>((size_t)(b->n_nodes + (int64_t)kResTabPad * b->n_graphs));
     t.col_r = c.template take<int32_t>(
         (size_t)(b->nnz + (int64_t)kResArcPerNode * b->n_nodes + (int64_t)kResArcPerGraph * b->n_graphs));
+    t.sorted_r = c.template take<int32_t>((size_t)std::max<int64_t>(b->nnz, 1));
     t.deg = c.template take<float>((size_t)b->n_nodes);
     t.invd = c.template take<float>((size_t)b->n_nodes);
     // 1/Delta pool with rows padded to 32 floats: sum_g k (k + 31) <= pool + 31 n_nodes
@@ -535,7 +537,8 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     const int G = b->n_graphs;
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[0], s));
     launch_degree(b->row_ptr, nullptr, b->n_nodes, w.deg, w.invd, s);
-    launch_res_layout(b->row_ptr, b->col_idx, nullptr, w.invd, b->node_off, 0, G, w.slots, w.col_r, nullptr, s);
+    launch_res_layout(b->row_ptr, b->col_idx, nullptr, w.invd, b->node_off, 0, G, w.slots, w.col_r, nullptr,
+                      w.sorted_r, nullptr, s);
     hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, b->node_off, G, w.plan);
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[1], s));
 

@@ -22,6 +22,8 @@ struct PprWs {
     double* resid;
     int32_t* col_r;  // resident tile: arc copy in group layout
     float* w_r;
+    int32_t* sorted_r;  // resident tile: arcs grouped by LDS bank class (layout staging)
+    float* sorted_w;
     MidWs mid;       // mid-size kernel: plan and arc stream
     float* ya;       // streaming SpMM: iterate ping-pong
     float* yb;
@@ -42,6 +44,8 @@ void ppr_ws_layout(Cursor& c, int n, int64_t nnz, bool weighted, int n_src, PprW
         t.slots = c.template take<ResSlot>((size_t)n + kResTabPad);
         t.col_r = c.template take<int32_t>((size_t)res_arc_words(nnz, n));
         t.w_r = weighted ? c.template take<float>((size_t)res_arc_words(nnz, n)) : nullptr;
+        t.sorted_r = c.template take<int32_t>((size_t)std::max<int64_t>(nnz, 1));
+        t.sorted_w = weighted ? c.template take<float>((size_t)std::max<int64_t>(nnz, 1)) : nullptr;
     }
     if (mid) {
         const int64_t groups = mid_stream_groups(n, nnz);
@@ -79,6 +83,6 @@ void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int3
                  double* resid, const PprWs& w, hipStream_t s);
 void launch_res_layout(const int32_t* row_ptr, const int32_t* col_idx, const float* weight, const float* invd,
                        const int64_t* node_off, int32_t n_single, int32_t blocks, ResSlot* slots, int32_t* arcs,
-                       float* warcs, hipStream_t s);
+                       float* warcs, int32_t* sorted, float* wsorted, hipStream_t s);
 
 }  // namespace pprviz

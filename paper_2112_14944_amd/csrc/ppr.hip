@@ -87,8 +87,9 @@ struct ResDealSet {
     int64_t base;
     bool over;      // NaN layout: each row holds only its own offset
     const int32_t* row_ptr;
-    const int32_t* col_idx;
-    const float* weight;
+    const int32_t* sorted;  // each row's arcs as LDS offsets, grouped by class (CSR order within a class)
+    const float* wsorted;   // their weights, or nullptr
+    const int32_t (*cstart)[4];  // per row: first arc of each class within its group of sorted
 };
 
 // Fills the set's rows position by position.  At position m the rows choose
@@ -124,15 +125,11 @@ __device__ __forceinline__ void res_deal_set(const ResDealSet& d, const int rr[4
         }
         rem[i] = re[i] - rs;
 #pragma unroll
-        for (int c = 0; c < M; ++c) cur[i][c] = re[i];
-        for (int e = re[i] - 1; e >= rs; --e) {
-            const int c = (int)((d.col_idx[e] - d.base) & (M - 1));
-#pragma unroll
-            for (int cc = 0; cc < M; ++cc)
-                if (cc == c) {
-                    ++cnt[i][cc];
-                    cur[i][cc] = e;
-                }
+        for (int c = 0; c < M; ++c) {
+            const int c0 = d.cstart[v[i]][c];
+            const int c1 = c + 1 < M ? d.cstart[v[i]][c + 1] : re[i] - rs;
+            cnt[i][c] = c1 - c0;
+            cur[i][c] = rs + c0;
         }
     }
     for (int mb = 0; mb < d.L; mb += M) {
@@ -169,11 +166,8 @@ __device__ __forceinline__ void res_deal_set(const ResDealSet& d, const int rr[4
 #pragma unroll
                 for (int c = 0; c < M; ++c) {
                     if (c != pick) continue;
-                    const int e = cur[i][c];
-                    put(i, m, (int)(d.col_idx[e] - d.base) * d.stride, d.weight ? d.weight[e] : 0.f);
-                    int f = e + 1;
-                    while (f < re[i] && (int)((d.col_idx[f] - d.base) & (M - 1)) != c) ++f;
-                    cur[i][c] = f;
+                    const int e = cur[i][c]++;
+                    put(i, m, d.sorted[e], d.wsorted ? d.wsorted[e] : 0.f);
                     --cnt[i][c];
                 }
                 --rem[i];
@@ -202,9 +196,11 @@ __global__ __launch_bounds__(256) void res_layout_kernel(const int32_t* __restri
                                                         const float* __restrict__ invd,
                                                         const int64_t* __restrict__ node_off, int32_t n_single,
                                                         ResSlot* __restrict__ slots, int32_t* __restrict__ arcs,
-                                                        float* __restrict__ warcs) {
+                                                        float* __restrict__ warcs, int32_t* __restrict__ sorted,
+                                                        float* __restrict__ wsorted) {
     constexpr int kMaxRows = 4096;
     __shared__ uint32_t key[kMaxRows];
+    __shared__ int32_t cstart[Res<16>::NMAX][4];
     __shared__ int64_t goff[kResMaxGroups + 1];
     __shared__ int32_t ghalves[kResMaxGroups];
     const int g = blockIdx.x;
@@ -244,6 +240,31 @@ __global__ __launch_bounds__(256) void res_layout_kernel(const int32_t* __restri
                 }
             }
             __syncthreads();
+        }
+    }
+    // each row's arcs as LDS offsets, grouped by bank class (CSR order within
+    // a class), and where each class starts
+    for (int v = threadIdx.x; v < n; v += 256) {
+        const int rs = row_ptr[base + v], re = row_ptr[base + v + 1];
+        int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+        for (int e = rs; e < re; ++e) {
+            const int c = (int)((col_idx[e] - base) & (M - 1));
+            c0 += c == 0;
+            c1 += c == 1;
+            c2 += c == 2;
+            c3 += c == 3;
+        }
+        int pos[4] = {rs, rs + c0, rs + c0 + c1, rs + c0 + c1 + c2};
+        cstart[v][0] = 0;
+        cstart[v][1] = c0;
+        cstart[v][2] = c0 + c1;
+        cstart[v][3] = c0 + c1 + c2;
+        for (int e = rs; e < re; ++e) {
+            const int u = (int)(col_idx[e] - base);
+            const int c = u & (M - 1);
+            const int at = c == 0 ? pos[0]++ : (c == 1 ? pos[1]++ : (c == 2 ? pos[2]++ : pos[3]++));
+            sorted[at] = u * stride;
+            if (wsorted) wsorted[at] = weight[e];
         }
     }
     const int ng = (n + GW - 1) / GW;
@@ -286,7 +307,7 @@ __global__ __launch_bounds__(256) void res_layout_kernel(const int32_t* __restri
     for (int t = threadIdx.x; t < ng * 4; t += 256) {
         const int gi = t >> 2;
         ResDealSet d;
-        d.L = over ? 16 : ghalves[gi] * 8;
+        d.L = over ? 8 : ghalves[gi] * 8;
         d.words = over ? 16 : (ghalves[gi] + 1) / 2 * 16;
         d.ca = arcs + tb.cbase + (over ? (int64_t)gi * 16 * GW : goff[gi]);
         d.wa = warcs ? warcs + tb.cbase + (over ? (int64_t)gi * 16 * GW : goff[gi]) : nullptr;
@@ -296,8 +317,9 @@ __global__ __launch_bounds__(256) void res_layout_kernel(const int32_t* __restri
         d.base = base;
         d.over = over;
         d.row_ptr = row_ptr;
-        d.col_idx = col_idx;
-        d.weight = weight;
+        d.sorted = sorted;
+        d.wsorted = weight ? wsorted : nullptr;
+        d.cstart = cstart;
         int rr[4];
         res_conflict_set(M, t & 3, rr);
         int v[4];
@@ -314,9 +336,9 @@ __global__ __launch_bounds__(256) void res_layout_kernel(const int32_t* __restri
 
 void launch_res_layout(const int32_t* row_ptr, const int32_t* col_idx, const float* weight, const float* invd,
                        const int64_t* node_off, int32_t n_single, int32_t blocks, ResSlot* slots, int32_t* arcs,
-                       float* warcs, hipStream_t s) {
+                       float* warcs, int32_t* sorted, float* wsorted, hipStream_t s) {
     hipLaunchKernelGGL(res_layout_kernel, dim3(blocks), dim3(256), 0, s, row_ptr, col_idx, weight, invd, node_off,
-                       n_single, slots, arcs, warcs);
+                       n_single, slots, arcs, warcs, sorted, wsorted);
 }
 
 template <int COLS, bool WEIGHTED>
@@ -370,7 +392,7 @@ void ppr_forward(const ppr_csr* g, const int32_t* src, int32_t n_src, const int3
     const int n = g->n;
     if (use_resident(n)) {
         launch_res_layout(g->row_ptr, g->col_idx, g->weight, invd, nullptr, n, 1, w.slots, w.col_r,
-                          g->weight ? w.w_r : nullptr, s);
+                          g->weight ? w.w_r : nullptr, w.sorted_r, g->weight ? w.sorted_w : nullptr, s);
         ResArgs a;
         a.slots = w.slots;
         a.arcs = w.col_r;
