@@ -49,7 +49,8 @@ def source_hash(files):
 
 
 KERNEL_SOURCES = {
-    "batch_ppr_kernel": ["paper_2112_14944_amd/csrc/ppr_core.hpp", "paper_2112_14944_amd/csrc/batch.hip"],
+    "batch_ppr_kernel": ["paper_2112_14944_amd/csrc/ppr_core.hpp", "paper_2112_14944_amd/csrc/ppr.hip",
+                         "paper_2112_14944_amd/csrc/batch.hip"],
     "batch_pair_kernel": ["paper_2112_14944_amd/csrc/layout_core.hpp", "paper_2112_14944_amd/csrc/batch.hip"],
 }
 
