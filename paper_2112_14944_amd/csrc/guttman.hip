@@ -22,6 +22,7 @@
 #include <algorithm>
 
 #include "layout_core.hpp"
+#include "ppr_core.hpp"
 
 namespace pprviz {
 
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(256) void cg_direction_kernel(int32_t k, int32_t it
 // are dealt to the 16 waves round-robin; each row's pair sums use the same
 // per-lane order and wave tree as cg_rows_kernel, the dot products are FP64
 // wave trees whose 16 wave sums are added in wave order.
-constexpr int kCgBatchMaxN = 2304;  // the batch's largest subgraph
+constexpr int kCgBatchMaxN = Res<16>::NMAX;  // the batch's largest subgraph (2304, the resident PPR tile's limit)
 constexpr int kCgBatchThreads = 1024;
 constexpr int kCgBatchWaves = kCgBatchThreads / kWave;
 
