@@ -42,7 +42,7 @@ struct __attribute__((aligned(16))) StripRec {
 struct BatchPlan {
     int32_t* order;      // [G] subgraph ids, largest first
     int64_t* tile_pre;   // [G+1] prefix of PPR tiles in LPT order
-    int64_t* pd_pre;     // [G+1] prefix of 64x64 PDist tiles (subgraph order)
+    int64_t* pd_pre;     // [G+1] prefix of 64x64 PDist tile pairs (I <= J; subgraph order)
     int64_t* rb_pre;     // [G+1] prefix of 16-row layout blocks (subgraph order)
     int32_t* pd_graph;   // subgraph of each PDist tile item
     int32_t* rb_graph;   // subgraph of each layout row-block item
@@ -101,7 +101,7 @@ __device__ __forceinline__ int64_t plan_count(int which, int n) {
     const int64_t T = (n + kPT - 1) / kPT;
     switch (which) {
         case 0: return tiles_of(n);                                          // PPR source tiles
-        case 1: return T * T;                                                // PDist 64x64 tiles
+        case 1: return T * (T + 1) / 2;                                      // PDist 64x64 tile pairs
         case 2: return (n + kLayoutRowsPerBlock - 1) / kLayoutRowsPerBlock;  // stress row blocks
         case 3: return strip_count(T);                                       // layout strips (S, J)
         case 4: return T;                                                    // 64-row tiles
@@ -290,16 +290,22 @@ __global__ __launch_bounds__(kResThreads) void batch_ppr_kernel(BatchArgs b, Bat
     }
 }
 
-// PDist of every subgraph, 64x64 tiles; also writes 1/Delta (zero diagonal)
-// for the layout sweeps, with the same reciprocal the single-layout kernel
-// evaluates per pair.
-__global__ __launch_bounds__(256) void batch_pdist_kernel(const int64_t* __restrict__ node_off,
+// PDist of every subgraph by 64x64 tile pairs (I, J), I <= J: both tiles of
+// pi_d, (I, J) and (J, I), are read once into LDS, and Eq. eq:pprdist's
+// symmetric z = pi_d(i, j) + pi_d(j, i) gives both tiles of Delta (the same
+// sum in the same order as an element-wise evaluation, so the result is
+// bit-identical to the single-graph kernel's); also writes 1/Delta (zero
+// diagonal) for the layout sweeps, with the same reciprocal the
+// single-layout kernel evaluates per pair.
+constexpr int kPdistThreads = 512;
+
+__global__ __launch_bounds__(kPdistThreads) void batch_pdist_kernel(const int64_t* __restrict__ node_off,
                                                           const int64_t* __restrict__ mat_off, int32_t G,
                                                           const int64_t* __restrict__ pd_pre,
                                                           const int32_t* __restrict__ pd_graph,
                                                           const float* __restrict__ pid, float* __restrict__ delta,
                                                           const int64_t* __restrict__ iv_pre, float* __restrict__ inv) {
-    __shared__ float tt[64][65];
+    __shared__ float ta[64][65], tb[64][65];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int64_t total = pd_pre[G];
@@ -307,26 +313,45 @@ __global__ __launch_bounds__(256) void batch_pdist_kernel(const int64_t* __restr
         const int g = pd_graph[item];
         const int k = graph_n(node_off, g);
         const int nt = (k + 63) / 64;
-        const int64_t local = item - pd_pre[g];
-        const int64_t i0 = (local / nt) * 64, j0 = (local % nt) * 64;
+        // item -> (I, J), I <= J, row by row over the upper triangle of tiles
+        int I = 0;
+        int64_t rem = item - pd_pre[g];
+        while (rem >= nt - I) {
+            rem -= nt - I;
+            ++I;
+        }
+        const int J = I + (int)rem;
+        const int64_t i0 = (int64_t)I * 64, j0 = (int64_t)J * 64;
         const float* P = pid + mat_off[g];
         float* D = delta + mat_off[g];
         float* V = inv + iv_pre[g];
         const int64_t ldv = inv_ld(k);
         const float hi = pdist_hi(k);
         __syncthreads();
-        for (int jj = w; jj < 64; jj += 4) {
-            const int64_t j = j0 + jj, i = i0 + lane;
-            tt[jj][lane] = (j < k && i < k) ? P[j * k + i] : 0.f;
+        // ta = tile (I, J) of pi_d, tb = tile (J, I)
+        for (int rr = w; rr < 64; rr += kPdistThreads / 64) {
+            ta[rr][lane] = (i0 + rr < k && j0 + lane < k) ? P[(i0 + rr) * k + j0 + lane] : 0.f;
+            if (I != J) tb[rr][lane] = (j0 + rr < k && i0 + lane < k) ? P[(j0 + rr) * k + i0 + lane] : 0.f;
         }
         __syncthreads();
-        for (int ii = w; ii < 64; ii += 4) {
-            const int64_t i = i0 + ii, j = j0 + lane;
+        // tile (I, J): z(i, j) = pi_d(i, j) + pi_d(j, i)
+        for (int rr = w; rr < 64; rr += kPdistThreads / 64) {
+            const int64_t i = i0 + rr, j = j0 + lane;
             if (i >= k || j >= k) continue;
-            const float z = P[i * k + j] + tt[lane][ii];
+            const float z = ta[rr][lane] + (I != J ? tb[lane][rr] : ta[lane][rr]);
             const float dv = (i == j) ? 0.f : pdist_value(z, hi);
             D[i * k + j] = dv;
             V[i * ldv + j] = (i == j) ? 0.f : __builtin_amdgcn_rcpf(dv);
+        }
+        if (I == J) continue;
+        // tile (J, I): z(j, i) = pi_d(j, i) + pi_d(i, j)
+        for (int rr = w; rr < 64; rr += kPdistThreads / 64) {
+            const int64_t j = j0 + rr, i = i0 + lane;
+            if (i >= k || j >= k) continue;
+            const float z = tb[rr][lane] + ta[lane][rr];
+            const float dv = pdist_value(z, hi);
+            D[j * k + i] = dv;
+            V[j * ldv + i] = __builtin_amdgcn_rcpf(dv);
         }
     }
 }
@@ -565,7 +590,7 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[2], s));
 
     const unsigned grid = (unsigned)cus * 8;
-    hipLaunchKernelGGL(batch_pdist_kernel, dim3(grid), dim3(256), 0, s, b->node_off, b->mat_off, G, w.plan.pd_pre,
+    hipLaunchKernelGGL(batch_pdist_kernel, dim3(grid), dim3(kPdistThreads), 0, s, b->node_off, b->mat_off, G, w.plan.pd_pre,
                        w.plan.pd_graph, dppr_pool, delta_pool, w.plan.iv_pre, w.inv);
     const unsigned pgrid = (unsigned)cus * pair_blocks_per_cu<kPairStep>();
     const unsigned wgrid = (unsigned)cus * pair_blocks_per_cu<kPairW>();
