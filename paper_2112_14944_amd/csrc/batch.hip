@@ -28,12 +28,12 @@ namespace pprviz {
 constexpr int kBatchMaxN = Res<16>::NMAX;  // 2304
 constexpr int kPlanThreads = 1024;
 
-// One layout strip with everything its wave needs to start, so that a strip
-// costs one scalar load of its record (issued a strip ahead) before its 1/Delta
-// stream starts.
+// One layout task (up to kStripGroup strips of a super-row) with everything
+// its wave needs to start, so that a task costs one scalar load of its record
+// before its 1/Delta stream starts.
 struct __attribute__((aligned(16))) StripRec {
     int32_t k;     // subgraph size
-    int32_t sj;    // S << 16 | J
+    int32_t sj;    // S << 16 | J0
     int64_t node;  // first node of the subgraph (positions)
     int64_t iv;    // offset of its 1/Delta block
     int64_t pb;    // offset of its partial blocks
@@ -46,13 +46,13 @@ struct BatchPlan {
     int64_t* rb_pre;     // [G+1] prefix of 16-row layout blocks (subgraph order)
     int32_t* pd_graph;   // subgraph of each PDist tile item
     int32_t* rb_graph;   // subgraph of each layout row-block item
-    int64_t* pt_pre;     // [G+1] prefix of the layout sweeps' strips (256 rows x 64 columns)
-    StripRec* strip_tab; // [pt_pre[G]] layout strips, largest first
+    int64_t* pt_pre;     // [G+1] prefix of the layout sweeps' tasks (256 rows x up to 256 columns)
+    StripRec* strip_tab; // [pt_pre[G]] layout tasks, largest first
     int64_t* rt_pre;     // [G+1] prefix of 64-row tiles (sweep finalize items)
     int32_t* rt_graph;   // subgraph of each 64-row tile
     int64_t* pb_pre;     // [G+1] prefix of the partial blocks, T*T*64 floats per subgraph
     int64_t* iv_pre;     // [G+1] prefix of the 1/Delta pool, k rows of inv_ld(k) floats per subgraph
-    int32_t* counter;    // [3] PPR task queue heads, one per tile width
+    int32_t* counter;    // [4] PPR task queue heads, one per tile width; layout task queue head
     int32_t* cls_pos;    // [4] first LPT position of the 16-, 32- and 64-column classes, then G
 };
 
@@ -103,23 +103,28 @@ __device__ __forceinline__ int64_t plan_count(int which, int n) {
         case 0: return tiles_of(n);                                          // PPR source tiles
         case 1: return T * (T + 1) / 2;                                      // PDist 64x64 tile pairs
         case 2: return (n + kLayoutRowsPerBlock - 1) / kLayoutRowsPerBlock;  // stress row blocks
-        case 3: return strip_count(T);                                       // layout strips (S, J)
+        case 3: return strip_task_count(T);                                  // layout tasks (S, J0)
         case 4: return T;                                                    // 64-row tiles
         case 5: return T * T * kPT;                                          // partial-block floats
         default: return (int64_t)n * inv_ld(n);                              // 1/Delta pool floats
     }
 }
 
-// Size class of a strip for the largest-first order: its pair count (live
-// rows times columns, at most 256 x 64) in steps of 64, largest first.
-constexpr int kStripClasses = kStripBlocks * kPT * kPT / 64;
+// Size class of a task for the largest-first order: its pair count (live
+// rows times columns of each of its strips, at most 256 x 256) in steps of
+// 64, largest first.
+constexpr int kStripClasses = kStripGroup * kStripBlocks * kPT * kPT / 64;
 
-__device__ __forceinline__ int strip_class(int k, int T, int S, int J) {
-    const int d = J - kStripBlocks * S;
-    const int nl = min(kStripBlocks, min(T - kStripBlocks * S, d + 1));
-    const int rows = min(nl * kPT, k - kStripBlocks * S * kPT);
-    const int cols = min(kPT, k - J * kPT);
-    return (kStripBlocks * kPT * kPT - rows * cols) / 64;
+__device__ __forceinline__ int strip_class(int k, int T, int S, int J0) {
+    int pairs = 0;
+    for (int J = J0; J < min(T, J0 + kStripGroup); ++J) {
+        const int d = J - kStripBlocks * S;
+        const int nl = min(kStripBlocks, min(T - kStripBlocks * S, d + 1));
+        const int rows = min(nl * kPT, k - kStripBlocks * S * kPT);
+        const int cols = min(kPT, k - J * kPT);
+        pairs += rows * cols;
+    }
+    return (kStripGroup * kStripBlocks * kPT * kPT - pairs) / 64;
 }
 
 __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t* __restrict__ node_off, int32_t G,
@@ -183,21 +188,21 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t*
     for (int g = tid; g < G; g += kPlanThreads) {
         for (int64_t i = p.rt_pre[g]; i < p.rt_pre[g + 1]; ++i) p.rt_graph[i] = g;
     }
-    // Layout strips of every subgraph, by size largest first (a counting sort
-    // over size classes of 64 pairs), so that the sweeps' static deal of
-    // strips to waves is even.  Which wave runs a strip never changes a sum:
-    // each strip writes its own partial slots.
+    // Layout tasks of every subgraph, by size largest first (a counting sort
+    // over size classes of 64 pairs), so that the sweeps' queue hands out the
+    // largest first.  Which wave runs a task never changes a sum: each task
+    // writes its own partial slots.
     __shared__ int32_t scls[kStripClasses];
     for (int i = tid; i < kStripClasses; i += kPlanThreads) scls[i] = 0;
     __syncthreads();
     for (int g = tid; g < G; g += kPlanThreads) {
         const int k = graph_n(node_off, g);
         const int T = (k + kPT - 1) / kPT;
-        const int ns = (int)strip_count(T);
+        const int ns = (int)strip_task_count(T);
         for (int t = 0; t < ns; ++t) {
-            int S, J;
-            strip_sj(t, T, S, J);
-            atomicAdd(&scls[strip_class(k, T, S, J)], 1);
+            int S, J0;
+            strip_task_sj(t, T, S, J0);
+            atomicAdd(&scls[strip_class(k, T, S, J0)], 1);
         }
     }
     __syncthreads();
@@ -213,14 +218,14 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t*
     for (int g = tid; g < G; g += kPlanThreads) {
         const int k = graph_n(node_off, g);
         const int T = (k + kPT - 1) / kPT;
-        const int ns = (int)strip_count(T);
+        const int ns = (int)strip_task_count(T);
         for (int t = 0; t < ns; ++t) {
-            int S, J;
-            strip_sj(t, T, S, J);
-            const int pos = atomicAdd(&scls[strip_class(k, T, S, J)], 1);
+            int S, J0;
+            strip_task_sj(t, T, S, J0);
+            const int pos = atomicAdd(&scls[strip_class(k, T, S, J0)], 1);
             StripRec r;
             r.k = k;
-            r.sj = (S << 16) | J;
+            r.sj = (S << 16) | J0;
             r.node = node_off[g];
             r.iv = p.iv_pre[g];
             r.pb = p.pb_pre[g];
@@ -240,7 +245,7 @@ __global__ __launch_bounds__(kPlanThreads) void batch_plan_kernel(const int64_t*
     }
     __syncthreads();
     if (tid == 0) {
-        p.counter[0] = p.counter[1] = p.counter[2] = 0;
+        p.counter[0] = p.counter[1] = p.counter[2] = p.counter[3] = 0;
         p.cls_pos[0] = 0;
         p.cls_pos[1] = cls_cnt[0];
         p.cls_pos[2] = cls_cnt[0] + cls_cnt[1];
@@ -337,7 +342,12 @@ __global__ __launch_bounds__(kPdistThreads) void batch_pdist_kernel(const int64_
         // tile (I, J): z(i, j) = pi_d(i, j) + pi_d(j, i)
         for (int rr = w; rr < 64; rr += kPdistThreads / 64) {
             const int64_t i = i0 + rr, j = j0 + lane;
-            if (i >= k || j >= k) continue;
+            if (i >= k || j >= ldv) continue;
+            if (j >= k) {
+                // row padding of 1/Delta: zeros, which the strips read as absent pairs
+                V[i * ldv + j] = 0.f;
+                continue;
+            }
             const float z = ta[rr][lane] + (I != J ? tb[lane][rr] : ta[lane][rr]);
             const float dv = (i == j) ? 0.f : pdist_value(z, hi);
             D[i * k + j] = dv;
@@ -390,37 +400,41 @@ __global__ __launch_bounds__(256) void batch_layout_kernel(const int64_t* __rest
     }
 }
 
-// Strip pass over every subgraph (see strip): wave w of the grid takes
-// strips w, w + W, w + 2W, ... (W waves in all) of the plan's largest-first
-// strip table, a static deal.
+// Task pass over every subgraph (see strip_task): wave w of the grid starts
+// with task w of the plan's largest-first table, then takes the next task
+// nobody has taken from the queue head (zeroed by the plan kernel and by
+// every finalize launch), so that the waves finish together.  The next
+// index is claimed at the start of a task and read at its end.
 template <int MODE>
 __global__ __launch_bounds__(256) void batch_pair_kernel(const int64_t* __restrict__ pt_pre, int32_t G,
                                                          const StripRec* __restrict__ strip_tab,
                                                          const float* __restrict__ inv,
                                                          const float2* __restrict__ x, float* __restrict__ px,
-                                                         float* __restrict__ py) {
+                                                         float* __restrict__ py, int32_t* __restrict__ queue) {
     __shared__ StripLds<MODE> lds[4];
     const int wave = threadIdx.x >> 6;
-    const int64_t total = pt_pre[G];
-    const int64_t W = (int64_t)gridDim.x * 4;
-    int64_t item = __builtin_amdgcn_readfirstlane((int)((int64_t)blockIdx.x * 4 + wave));
+    const int lane = threadIdx.x & 63;
+    const int total = (int)pt_pre[G];
+    const int W = (int)gridDim.x * 4;
+    int item = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wave);
     if (item >= total) return;
-    StripRec cur = strip_tab[item];
+    StripPend pend = strip_pend_none(px);
+    // lane 0 takes the queue's next index; the other lanes' increments go
+    // outside the resource, so that no branch (and no early wait) surrounds it
+    const __amdgpu_buffer_rsrc_t qr = __builtin_amdgcn_make_buffer_rsrc(queue, 0, 4, 0x00020000);
+    const int qoff = lane == 0 ? 0 : (int)kStripOutside;
     while (true) {
-        const int64_t next = item + W;
-        // the next record is loaded before this strip's work, so its latency
-        // overlaps the strip
-        StripRec nxt = cur;
-        if (next < total) nxt = strip_tab[next];
+        const StripRec cur = strip_tab[item];
+        const int claim = __builtin_amdgcn_raw_ptr_buffer_atomic_add_i32(1, qr, qoff, 0, 0);
         const int k = __builtin_amdgcn_readfirstlane(cur.k);
         const int sj = __builtin_amdgcn_readfirstlane(cur.sj);
         const int T = (k + kPT - 1) / kPT;
-        strip<MODE>(inv + cur.iv, inv_ld(k), k, x + cur.node, sj >> 16, sj & 0xffff, T, px + cur.pb, py + cur.pb,
-                    lds[wave]);
-        if (next >= total) break;
-        item = next;
-        cur = nxt;
+        strip_task<MODE>(inv + cur.iv, inv_ld(k), k, x + cur.node, sj >> 16, sj & 0xffff, T, px + cur.pb,
+                         py + cur.pb, lds[wave], pend);
+        item = W + __builtin_amdgcn_readfirstlane(claim);
+        if (item >= total) break;
     }
+    strip_pend_issue<MODE>(pend);
 }
 
 // Combine the partial blocks: one wave per 64-row block of a subgraph.
@@ -433,10 +447,13 @@ __global__ __launch_bounds__(256) void batch_pair_finalize_kernel(const int64_t*
                                                                   const float* __restrict__ py,
                                                                   const float2* __restrict__ x,
                                                                   float2* __restrict__ xout,
-                                                                  float* __restrict__ wsum) {
+                                                                  float* __restrict__ wsum,
+                                                                  int32_t* __restrict__ queue) {
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int64_t total = rt_pre[G];
+    // the next task pass starts its queue at zero (its launch follows this one)
+    if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0;
     for (int64_t item = (int64_t)blockIdx.x * 4 + wave; item < total; item += (int64_t)gridDim.x * 4) {
         const int g = rt_graph[item];
         const int k = graph_n(node_off, g);
@@ -507,7 +524,7 @@ static void batch_layout_ws(Cursor& c, const ppr_batch* b, BatchWs* w) {
     // sum_g ceil(n_g/16) <= n_nodes/16 + G
     t.plan.pd_graph = c.template take<int32_t>((size_t)(b->pool_size / 4096 + b->n_nodes / 32 + b->n_graphs + 1));
     t.plan.rb_graph = c.template take<int32_t>((size_t)(b->n_nodes / kLayoutRowsPerBlock + b->n_graphs + 1));
-    // strips: sum_g strip_count(T) <= sum_g T(T+1)/2 <= pool/8192 + 3 n_nodes/128 + G;
+    // tasks: sum_g strip_task_count(T) <= sum_g T(T+1)/2 <= pool/8192 + 3 n_nodes/128 + G;
     // 64-row tiles <= n_nodes/64 + G
     t.plan.pt_pre = c.template take<int64_t>((size_t)b->n_graphs + 1);
     t.plan.strip_tab = c.template take<StripRec>((size_t)(b->pool_size / 8192 + 3 * b->n_nodes / 128 + b->n_graphs + 1));
@@ -597,10 +614,10 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     const unsigned fgrid = (unsigned)cus * 8;
     // per-node weight sums, from the pair tiles in the order the sweeps use
     hipLaunchKernelGGL((batch_pair_kernel<kPairW>), dim3(wgrid), dim3(256), 0, s, w.plan.pt_pre, G, w.plan.strip_tab,
-                       w.inv, reinterpret_cast<const float2*>(x0), w.px, w.py);
+                       w.inv, reinterpret_cast<const float2*>(x0), w.px, w.py, w.plan.counter + 3);
     hipLaunchKernelGGL((batch_pair_finalize_kernel<kPairW>), dim3(fgrid), dim3(256), 0, s, b->node_off, G,
                        w.plan.rt_pre, w.plan.rt_graph, w.plan.pb_pre, w.px, w.py,
-                       reinterpret_cast<const float2*>(x0), nullptr, w.wsum);
+                       reinterpret_cast<const float2*>(x0), nullptr, w.wsum, w.plan.counter + 3);
     if (ev) PPRVIZ_HIP_TRY(hipEventRecord(ev[3], s));
 
     // Jacobi sweeps, ping-pong so that the last one lands in x_out.
@@ -614,9 +631,10 @@ static ppr_status batch_enqueue(const ppr_batch* b, float alpha, int32_t T, int3
     for (int it = 0; it < stress_iters; ++it) {
         float2* out = bufs[next];
         hipLaunchKernelGGL((batch_pair_kernel<kPairStep>), dim3(pgrid), dim3(256), 0, s, w.plan.pt_pre, G,
-                           w.plan.strip_tab, w.inv, cur, w.px, w.py);
+                           w.plan.strip_tab, w.inv, cur, w.px, w.py, w.plan.counter + 3);
         hipLaunchKernelGGL((batch_pair_finalize_kernel<kPairStep>), dim3(fgrid), dim3(256), 0, s, b->node_off, G,
-                           w.plan.rt_pre, w.plan.rt_graph, w.plan.pb_pre, w.px, w.py, cur, out, w.wsum);
+                           w.plan.rt_pre, w.plan.rt_graph, w.plan.pb_pre, w.px, w.py, cur, out, w.wsum,
+                           w.plan.counter + 3);
         cur = out;
         next ^= 1;
     }

@@ -205,41 +205,52 @@ __global__ __launch_bounds__(256) void layout_rows_kernel(const float* __restric
 //
 // A strip (S, J) is the 256 rows of super-row S, as four 64-row blocks
 // A = 4 S + r, against the 64 columns of block J (J >= 4 S).  Lane l holds
-// row 64 A + l of every block, and the wave walks the 64 columns j, reading
-// 1/Delta[j][i] for its four rows (one contiguous 1 KB piece of row j).  Row
+// the four consecutive rows 256 S + 4 l .. + 3 (all in block 4 S + l / 16),
+// and the wave walks the columns j, reading 1/Delta[j][i] for its four rows
+// with one 16-byte load (together one contiguous 1 KB piece of row j).  Row
 // block A takes every pair with the columns when A < J and feeds both ends,
 // its ordered pairs only when A == J (the diagonal block: rows only, each
 // pair seen from both ends), and nothing when A > J (the strip of J's
-// super-row has those pairs).  Which case holds is the same for the whole
-// wave.  Row sums stay in the lane; the column sums of 8 columns at a time go
-// through a small LDS block, where 8 lanes per column add 8 lanes' partials
-// each and three lane exchanges finish the column.
+// super-row has those pairs).  Column sums of 8 columns at a time go through
+// a small LDS block, where 8 lanes per column add 8 lanes' partials each and
+// three lane exchanges finish the column.
 //
-// Partials: P[A][J] (64 floats per component) holds row block A's sum over
-// the columns of block J (J >= A); P[J][S] (S < J / 4) holds column block
-// J's sum over the rows of super-row S.  These slot ranges are disjoint, and
+// A task is up to kStripGroup consecutive strips of one super-row, J0 = 4 S +
+// kStripGroup m .. J0 + nJ - 1: row sums stay in registers across its column
+// blocks, so a row's partial is written once per task, not once per strip
+// (the sweep is bound by its 1/Delta stream, and writes interleaved with that
+// stream cost far more read bandwidth than their bytes).
+//
+// Partials, 64 floats per slot and component in a [T][T] grid per subgraph:
+// row block A's sum over a task's columns goes to slot (A, max(A, J0)) (the
+// diagonal task J0 = 4 S into (A, A), the others into (A, J0) with J0 > A);
+// column block J's sum over super-row S goes to (J, S), written only for
+// J > 4 S (where some row block lies left of J).  Row slots have a second
+// index >= A and column slots one < A / 4 + 1 <= A, so the two never meet.
 // strip_finalize adds a node's slots in one fixed order, so the result does
-// not depend on which wave ran which strip.
+// not depend on which wave ran which task.
 constexpr int kPT = 64;
 constexpr int kStripBlocks = 4;
-constexpr int kPTChunk = 8;  // columns per LDS column exchange
+constexpr int kPTChunk = 8;     // columns per LDS column exchange
+constexpr int kStripGroup = 4;  // column blocks per task
 
-// Strips of a subgraph with T column blocks: super-row S holds the strips
-// J = 4 S .. T - 1.
-__host__ __device__ __forceinline__ int64_t strip_count(int64_t T) {
-    const int64_t S = (T + kStripBlocks - 1) / kStripBlocks;
-    return T * S - 2 * S * (S - 1);
+// Tasks of a subgraph with T column blocks: super-row S (of U = ceil(T / 4))
+// holds U - S of them.
+__host__ __device__ __forceinline__ int64_t strip_task_count(int64_t T) {
+    const int64_t U = (T + kStripBlocks - 1) / kStripBlocks;
+    return U * (U + 1) / 2;
 }
 
-// Strip index t of a T-block subgraph -> (S, J).
-__device__ __forceinline__ void strip_sj(int t, int T, int& S, int& J) {
+// Task index t of a T-block subgraph -> (S, J0).
+__device__ __forceinline__ void strip_task_sj(int t, int T, int& S, int& J0) {
+    const int U = (T + kStripBlocks - 1) / kStripBlocks;
     int s = 0;
-    while (t >= T - kStripBlocks * s) {
-        t -= T - kStripBlocks * s;
+    while (t >= U - s) {
+        t -= U - s;
         ++s;
     }
     S = s;
-    J = kStripBlocks * s + t;
+    J0 = kStripBlocks * s + kStripGroup * t;
 }
 
 enum { kPairStep = 0, kPairW = 1 };
@@ -256,107 +267,71 @@ struct StripLds<kPairW> {
     float v[kPTChunk][kWave];
 };
 
-// The live row blocks of a strip are a prefix: blocks 4 S .. 4 S + NL - 1,
-// all taking full pairs except the last, which is the diagonal block J when
-// DIAG.  Both are template parameters, so every branch on a block's role is
-// resolved at compile time.
-template <int NL, bool DIAG>
-struct StripShape {
-    static constexpr bool full(int r) { return r < NL - (DIAG ? 1 : 0); }
-    static constexpr bool live(int r) { return r < NL; }
-    static constexpr bool any_full = NL - (DIAG ? 1 : 0) > 0;
-};
-
 // Byte offset past every subgraph block of the 1/Delta pool: a buffer load
 // there returns 0 and touches no memory.
 constexpr uint32_t kStripOutside = 0x80000000u;
 
+// What the column exchange of a task needs.
 struct StripCtx {
-    __amdgpu_buffer_rsrc_t mr;  // 1/Delta rows from column 256 S on
-    int lane, S, J, T, j0, ncol, cc, cp;
-    uint32_t voff[kStripBlocks];  // lane's byte offset in a row, kStripOutside for rows >= k
-    float2 xi[kStripBlocks];
-    float2 xcol;                  // X of column 64 J + lane (read out per column with readlane)
+    int lane, S, T, cc, cp;
+    __amdgpu_buffer_rsrc_t prx, pry;  // the subgraph's partial blocks ([T][T][64] floats each)
 };
 
-// Loads of NC columns for the strip's live row blocks; nval is
-// the number of those columns that exist.  Rows and columns outside the
-// subgraph read zeros through the buffer resource, so no load is predicated.
-template <typename SH, bool FULLCOLS, int NC>
-__device__ __forceinline__ void strip_load(const StripCtx& t, int64_t ld, int jq, int nval,
-                                           float (&mv)[kStripBlocks][NC]) {
-#pragma unroll
-    for (int s = 0; s < NC; ++s) {
-        const bool col_ok = FULLCOLS || s < nval;
-        const int soff = col_ok ? (int)((int64_t)(jq + s) * ld * 4) : (int)(kStripOutside >> 1);
-#pragma unroll
-        for (int r = 0; r < kStripBlocks; ++r) {
-            if (!SH::live(r)) continue;
-            mv[r][s] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(t.mr, (int)t.voff[r], soff, 0));
-        }
-    }
+typedef unsigned int StripU4 __attribute__((ext_vector_type(4)));
+
+// s_waitcnt immediate that waits until at most N vector memory operations
+// are outstanding and leaves the export and LDS/scalar counters alone
+// (vmcnt in bits 3:0 and 15:14, expcnt 6:4 = 7, lgkmcnt 11:8 = 15).
+template <int N>
+constexpr int kWaitVmcnt = (N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8);
+
+// A strip's row partials, stored by the next strip of the same wave once
+// that strip's loads are in flight.  Loads and stores retire in one ordered
+// count, so a store issued at the end of a strip would hold up the first
+// wait of the next one until the write is acknowledged.
+struct StripPend {
+    StripU4 vx, vy;
+    __amdgpu_buffer_rsrc_t rx, ry;
+    int off;  // byte offset in the partial blocks; kStripOutside: nothing to store
+};
+
+// Nothing pending: stores through empty resources.
+__device__ __forceinline__ StripPend strip_pend_none(float* __restrict__ any) {
+    StripPend p;
+    p.vx = p.vy = StripU4{0u, 0u, 0u, 0u};
+    p.rx = p.ry = __builtin_amdgcn_make_buffer_rsrc(any, 0, 0, 0x00020000);
+    p.off = (int)kStripOutside;
+    return p;
 }
 
-// Arithmetic of NC columns; their column terms go to LDS slots s0 .. s0 + NC - 1.
-template <int MODE, typename SH, bool FULLCOLS, int NC>
-__device__ __forceinline__ void strip_cols_math(const StripCtx& t, const float2* __restrict__ x, int32_t k, int jq,
-                                                int s0, const float (&mv)[kStripBlocks][NC],
-                                                float (&ax)[kStripBlocks], float (&ay)[kStripBlocks],
-                                                StripLds<MODE>& L) {
-#pragma unroll
-    for (int s = 0; s < NC; ++s) {
-        float cx = 0.f, cy = 0.f;
-        float2 xj = make_float2(0.f, 0.f);
-        if (MODE == kPairStep) {
-            // the column's position from the lane that loaded it: no memory
-            // access inside the loop besides the 1/Delta stream
-            const int c = jq - t.j0 + s;
-            xj.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t.xcol.x), c));
-            xj.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t.xcol.y), c));
-        }
-#pragma unroll
-        for (int r = 0; r < kStripBlocks; ++r) {
-            if (!SH::live(r)) continue;
-            const float inv = mv[r][s];
-            const float w = inv * inv;
-            if (MODE == kPairStep) {
-                const float dx = t.xi[r].x - xj.x;
-                const float dy = t.xi[r].y - xj.y;
-                const float r2 = fmaf(dx, dx, fmaf(dy, dy, kMinSq));
-                const float g = fmaf(inv, __builtin_amdgcn_rsqf(r2), -w);
-                ax[r] = fmaf(g, dx, ax[r]);
-                ay[r] = fmaf(g, dy, ay[r]);
-                if (SH::full(r)) {
-                    cx = fmaf(-g, dx, cx);
-                    cy = fmaf(-g, dy, cy);
-                }
-            } else {
-                ax[r] += w;
-                if (SH::full(r)) cx += w;
-            }
-        }
-        if constexpr (SH::any_full) {
-            if constexpr (MODE == kPairStep) L.v[s0 + s][t.lane] = make_float2(cx, cy);
-            else L.v[s0 + s][t.lane] = cx;
-        }
-        // keep each column's accumulations in place: sinking them to the end
-        // of the chunk would hold every pair's temporaries in registers
-#pragma unroll
-        for (int r = 0; r < kStripBlocks; ++r) {
-            if (!SH::live(r)) continue;
-            asm volatile("" : "+v"(ax[r]));
-            if (MODE == kPairStep) asm volatile("" : "+v"(ay[r]));
-        }
-    }
+template <int MODE>
+__device__ __forceinline__ void strip_pend_issue(const StripPend& p) {
+    __builtin_amdgcn_raw_buffer_store_b128(p.vx, p.rx, p.off, 0, 0);
+    if (MODE == kPairStep) __builtin_amdgcn_raw_buffer_store_b128(p.vy, p.ry, p.off, 0, 0);
 }
 
-// Column sums of one chunk (8 columns at jq): lane (cc, cp) adds the partials
-// of lanes 8 cp .. 8 cp + 7 for column cc, starting at lane 8 cp + cp so that
-// the 8 lanes of a column read 8 different bank groups; the column total goes
-// to slot P[J][S].
-template <int MODE, bool FULLCOLS>
-__device__ __forceinline__ void strip_columns(const StripCtx& t, int q, float* __restrict__ px,
-                                              float* __restrict__ py, StripLds<MODE>& L) {
+// Buffer resources over the partial blocks, so that a store from an idle
+// lane goes outside them instead of behind a branch.
+template <int MODE>
+__device__ __forceinline__ void strip_part_rsrc(StripCtx& t, float* __restrict__ px, float* __restrict__ py) {
+    const int bytes = t.T * t.T * kPT * 4;
+    t.prx = __builtin_amdgcn_make_buffer_rsrc(px, 0, bytes, 0x00020000);
+    t.pry = __builtin_amdgcn_make_buffer_rsrc(MODE == kPairStep ? py : px, 0, bytes, 0x00020000);
+}
+
+// Column sums of one chunk (columns c .. c + 7 of block J, ncol of whose
+// columns exist): lane (cc, cp) adds the partials of lanes 8 cp .. 8 cp + 7
+// for column cc, starting at lane 8 cp + cp so that the 8 lanes of a column
+// read 8 different bank groups, and three lane exchanges give every lane of
+// the group the column total.  Lane l keeps the total of column l of the
+// block (colx, coly), taken in the chunk that holds it, and the block's last
+// chunk (jend) stores the 64 totals as one 256-byte row per component into
+// slot (J, S), when J > 4 S (before that no row block lies left of J and the
+// sums are zero): whole lines, since lines written piecemeal while the
+// 1/Delta stream runs cost far more than their bytes.
+template <int MODE>
+__device__ __forceinline__ void strip_columns(const StripCtx& t, int J, int c, int ncol, bool jend, float& colx,
+                                              float& coly, StripLds<MODE>& L) {
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     float sx = 0.f, sy = 0.f;
 #pragma unroll
@@ -378,123 +353,149 @@ __device__ __forceinline__ void strip_columns(const StripCtx& t, int q, float* _
         sy += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sy), 0x4E, 0xf, 0xf, false));
         sy += __shfl_xor(sy, 4, kWave);
     }
-    const int jj = q * kPTChunk + t.cc;
-    if (t.cp == 0 && (FULLCOLS || jj < t.ncol)) {
-        const int64_t o = ((int64_t)t.J * t.T + t.S) * kPT + jj;
-        px[o] = sx;
-        if (MODE == kPairStep) py[o] = sy;
+    // column c + (l % 8) is held by lanes 8 (l % 8) .. + 7; lane l keeps it
+    // when it is column l, i.e. in chunk l / 8 of the block
+    const int src = 8 * (t.lane & 7);
+    const bool mine = (t.lane >> 3) == (c >> 3);
+    const float vx = __shfl(sx, src, kWave);
+    colx = mine ? vx : colx;
+    if (MODE == kPairStep) {
+        const float vy = __shfl(sy, src, kWave);
+        coly = mine ? vy : coly;
     }
+    const bool wr = jend && t.lane < ncol && J > kStripBlocks * t.S;
+    const int o = wr ? ((J * t.T + t.S) * kPT + t.lane) * 4 : (int)kStripOutside;
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(colx), t.prx, o, 0, 0);
+    if (MODE == kPairStep) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(coly), t.pry, o, 0, 0);
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
-// One strip.  MODE kPairStep: the position sums g (X_i - X_j) into (px, py);
-// kPairW: the weight sums w into px.  `m` is the subgraph's 1/Delta block
-// (k rows of ld floats, zero diagonal), px and py its partial blocks
-// ([T][T][64] floats).  FULLCOLS: all 64 columns of block J exist.  Loads of
-// the next group of columns are issued before the arithmetic of the current
-// one.
-template <int MODE, typename SH, bool FULLCOLS>
-__device__ __forceinline__ void strip_body(const float* __restrict__ m, int64_t ld, int32_t k,
-                                           const float2* __restrict__ x, int S, int J, int T,
-                                           float* __restrict__ px, float* __restrict__ py, StripLds<MODE>& L) {
-    StripCtx t;
-    t.lane = threadIdx.x & 63;
-    t.S = S;
-    t.J = J;
-    t.T = T;
-    t.j0 = J * kPT;
-    t.ncol = FULLCOLS ? kPT : min(kPT, k - t.j0);
-    t.cc = t.lane >> 3;
-    t.cp = t.lane & 7;
-#pragma unroll
-    for (int r = 0; r < kStripBlocks; ++r) {
-        const int i = (kStripBlocks * S + r) * kPT + t.lane;
-        const bool rok = SH::live(r) && i < k;
-        t.voff[r] = rok ? (uint32_t)((r * kPT + t.lane) * 4) : kStripOutside;
-        t.xi[r] = (MODE == kPairStep && rok) ? x[i] : make_float2(0.f, 0.f);
-    }
-    t.xcol = MODE == kPairStep ? x[min(t.j0 + t.lane, k - 1)] : make_float2(0.f, 0.f);
-    const int64_t c0 = (int64_t)S * kStripBlocks * kPT;
-    t.mr = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(m + c0), 0, (int)(((int64_t)k * ld - c0) * 4),
-                                             0x00020000);
-    float ax[kStripBlocks], ay[kStripBlocks];
-#pragma unroll
-    for (int r = 0; r < kStripBlocks; ++r) ax[r] = ay[r] = 0.f;
-    // two load groups of 4 columns per exchange chunk; each group's loads
-    // are issued one group ahead of its arithmetic
-    const int nq = (t.ncol + kPTChunk - 1) / kPTChunk;
-    constexpr int H = kPTChunk / 2;
-    float ha[kStripBlocks][H], hb[kStripBlocks][H];
-    strip_load<SH, FULLCOLS, H>(t, ld, t.j0, t.ncol, ha);
-    strip_load<SH, FULLCOLS, H>(t, ld, t.j0 + H, t.ncol - H, hb);
-#pragma nounroll
-    for (int q = 0; q < nq; ++q) {
-        const int jq = t.j0 + q * kPTChunk;
-        strip_cols_math<MODE, SH, FULLCOLS, H>(t, x, k, jq, 0, ha, ax, ay, L);
-        if (q + 1 < nq) strip_load<SH, FULLCOLS, H>(t, ld, jq + kPTChunk, t.ncol - (q + 1) * kPTChunk, ha);
-        strip_cols_math<MODE, SH, FULLCOLS, H>(t, x, k, jq + H, H, hb, ax, ay, L);
-        if (q + 1 < nq)
-            strip_load<SH, FULLCOLS, H>(t, ld, jq + kPTChunk + H, t.ncol - (q + 1) * kPTChunk - H, hb);
-        if constexpr (SH::any_full) strip_columns<MODE, FULLCOLS>(t, q, px, py, L);
-    }
-#pragma unroll
-    for (int r = 0; r < kStripBlocks; ++r) {
-        if (!SH::live(r)) continue;
-        const int A = kStripBlocks * S + r;
-        const int64_t o = ((int64_t)A * T + J) * kPT + t.lane;
-        px[o] = ax[r];
-        if (MODE == kPairStep) py[o] = ay[r];
-    }
-}
-
-// A strip whose 256 rows all lie in the subgraph and left of block J, and
-// whose 64 columns all exist (the bulk of every large subgraph): lane l owns
-// the four consecutive rows 256 S + 4 l .. + 3 and reads their 1/Delta values
-// of a column with one 16-byte load, a quarter of the load instructions of
-// strip_body.  Same pair terms, column exchange and partial slots.
-template <int MODE>
-__device__ __forceinline__ void strip_body_x4(const float* __restrict__ m, int64_t ld, int32_t k,
-                                              const float2* __restrict__ x, int S, int J, int T,
-                                              float* __restrict__ px, float* __restrict__ py,
-                                              StripLds<MODE>& L) {
+// A task in 16-byte form: lane l owns rows 256 S + 4 l .. + 3 of row block
+// A = 4 S + l / 16 and reads a column's four values with one 16-byte buffer
+// load; the task's columns (64 J0 on, nJ blocks) are one sequence of 8-column
+// chunks.  MASKED = false is a task whose 256 rows all lie in the subgraph
+// and left of J0 and whose columns all exist (the bulk of every large
+// subgraph).  MASKED = true is any other task: for column block J, lanes
+// with A > J read zeros (offset outside the resource); lanes of the diagonal
+// block A == J add to their own rows only, so their column terms are dropped
+// at the exchange; columns past k read zeros through the scalar offset, and
+// rows from k to the padded row length read the zeros written into the
+// padding of the 1/Delta rows.
+//
+// No memory operation depends on a branch: the prefetch after the last
+// chunk reads past the task's columns, which returns zeros without a memory
+// access, and partial stores of idle lanes go outside their resource.  The
+// compiler then waits for exactly the loads a chunk uses, with the next
+// chunk's loads still in flight.
+template <int MODE, bool MASKED>
+__device__ __forceinline__ void strip_task_body(const float* __restrict__ m, int64_t ld, int32_t k,
+                                                const float2* __restrict__ x, int S, int J0, int T,
+                                                float* __restrict__ px, float* __restrict__ py, StripLds<MODE>& L,
+                                                StripPend& pend) {
     constexpr int H = kPTChunk / 2;
     const int lane = threadIdx.x & 63;
-    const int i0 = S * kStripBlocks * kPT + 4 * lane;
+    const int A = S * kStripBlocks + lane / 16;
+    const int nJ = min(kStripGroup, T - J0);
+    const int c0 = S * kStripBlocks * kPT;
+    const int i0 = c0 + 4 * lane;
+    const int j0 = J0 * kPT;
+    // columns of the task that exist (at least one)
+    const int ncol = MASKED ? min(kPT * nJ, k - j0) : kPT * nJ;
+    // Positions of the lane's rows and of the task's columns (one float2 per
+    // lane and column block), through a buffer resource over the subgraph's
+    // k positions: rows and columns past k read zeros, and unlike plain loads
+    // from a read-only pointer these stay in place relative to the task's
+    // loads and stores (no load sits behind a branch, and the first wait
+    // finds only them ahead of the 1/Delta loads).
     float2 xi[4];
+    float2 xc[kStripGroup];
+    if constexpr (MODE == kPairStep) {
+        const __amdgpu_buffer_rsrc_t xr =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(x), 0, k * 8, 0x00020000);
+        if constexpr (MASKED) {
+            // clamped so that no load is partly outside the resource (and the
+            // four cannot be fused into wider ones); rows past k take 0
 #pragma unroll
-    for (int r = 0; r < 4; ++r) xi[r] = MODE == kPairStep ? x[i0 + r] : make_float2(0.f, 0.f);
-    const int j0 = J * kPT;
-    const float2 xcol = MODE == kPairStep ? x[j0 + lane] : make_float2(0.f, 0.f);
-    const float* __restrict__ rowp = m + i0;
+            for (int r = 0; r < 4; ++r) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b64(xr, min(i0 + r, k - 1) * 8, 0, 0);
+                const bool ok = i0 + r < k;
+                xi[r] = make_float2(ok ? __uint_as_float(v[0]) : 0.f, ok ? __uint_as_float(v[1]) : 0.f);
+            }
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const StripU4 v = __builtin_amdgcn_raw_buffer_load_b128(xr, i0 * 8 + 16 * h, 0, 0);
+                xi[2 * h] = make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+                xi[2 * h + 1] = make_float2(__uint_as_float(v[2]), __uint_as_float(v[3]));
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < kStripGroup; ++b) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(xr, (j0 + b * kPT + lane) * 8, 0, 0);
+            xc[b] = make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xi[r] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int b = 0; b < kStripGroup; ++b) xc[b] = make_float2(0.f, 0.f);
+    }
+    asm volatile("" ::: "memory");  // the position loads go out before the task's
     StripCtx t;
     t.lane = lane;
     t.S = S;
-    t.J = J;
     t.T = T;
-    t.j0 = j0;
-    t.ncol = kPT;
     t.cc = lane >> 3;
     t.cp = lane & 7;
-    float ax[4] = {0.f, 0.f, 0.f, 0.f}, ay[4] = {0.f, 0.f, 0.f, 0.f};
-    float4 ha[H], hb[H];
+    strip_part_rsrc<MODE>(t, px, py);
+    const __amdgpu_buffer_rsrc_t mr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(m + c0), 0, (int)(((int64_t)k * ld - c0) * 4), 0x00020000);
+    const bool rowok = !MASKED || i0 < ld;
+    // four loads of columns cg .. cg + 3 (one column block: 64 is a multiple of 4)
+    auto load4 = [&](int cg, StripU4 (&v)[H]) {
+        const int voff = (!MASKED || (rowok && A <= J0 + cg / kPT)) ? 16 * lane : (int)kStripOutside;
 #pragma unroll
-    for (int s = 0; s < H; ++s) {
-        ha[s] = *reinterpret_cast<const float4*>(rowp + (int64_t)(j0 + s) * ld);
-        hb[s] = *reinterpret_cast<const float4*>(rowp + (int64_t)(j0 + H + s) * ld);
-    }
-    auto math = [&](const float4 (&v)[H], int c0, int s0) {
+        for (int s = 0; s < H; ++s) {
+            const int c = cg + s;
+            const int soff = c < ncol ? (int)((int64_t)(j0 + c) * ld * 4) : (int)(kStripOutside >> 1);
+            v[s] = __builtin_amdgcn_raw_buffer_load_b128(mr, voff, soff, 0);
+        }
+    };
+    float ax[4] = {0.f, 0.f, 0.f, 0.f}, ay[4] = {0.f, 0.f, 0.f, 0.f};
+    float colx = 0.f, coly = 0.f;  // total of column l of the current block (lane l)
+    // The loop is entered with the memory operations outstanding in the order
+    // its back edge leaves them: four loads of the first half-chunk, four of
+    // the second, then as many stores as a chunk's column exchange makes (here
+    // the previous task's row partials).  The compiler merges the two orders
+    // when it places its waits; with the same order each wait covers only the
+    // loads a column uses.
+    StripU4 ha[H], hb[H];
+    load4(0, ha);
+    asm volatile("" ::: "memory");
+    load4(H, hb);
+    asm volatile("" ::: "memory");
+    strip_pend_issue<MODE>(pend);
+    // wait here for the positions only, so that they are not pending when the
+    // loop is entered
+    constexpr int kInFlight = 2 * H + (MODE == kPairStep ? 2 : 1);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt<kInFlight>);
+    asm volatile("" ::: "memory");
+    float2 xcol = xc[0];
+    auto math = [&](const StripU4 (&v)[H], int cb, int s0, bool full) {
 #pragma unroll
         for (int s = 0; s < H; ++s) {
             float cx = 0.f, cy = 0.f;
             float2 xj = make_float2(0.f, 0.f);
             if (MODE == kPairStep) {
-                xj.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xcol.x), c0 + s));
-                xj.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xcol.y), c0 + s));
+                // the column's position from the lane that loaded it: no
+                // memory access inside the loop besides the 1/Delta stream
+                xj.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xcol.x), cb + s));
+                xj.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xcol.y), cb + s));
             }
-            const float iv[4] = {v[s].x, v[s].y, v[s].z, v[s].w};
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float inv = iv[r];
+                const float inv = __uint_as_float(v[s][r]);
                 const float w = inv * inv;
                 if (MODE == kPairStep) {
                     const float dx = xi[r].x - xj.x;
@@ -510,8 +511,14 @@ __device__ __forceinline__ void strip_body_x4(const float* __restrict__ m, int64
                     cx += w;
                 }
             }
+            if (MASKED) {
+                cx = full ? cx : 0.f;
+                cy = full ? cy : 0.f;
+            }
             if constexpr (MODE == kPairStep) L.v[s0 + s][lane] = make_float2(cx, cy);
             else L.v[s0 + s][lane] = cx;
+            // keep each column's accumulations in place: sinking them to the
+            // end of the chunk would hold every pair's temporaries in registers
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 asm volatile("" : "+v"(ax[r]));
@@ -519,69 +526,71 @@ __device__ __forceinline__ void strip_body_x4(const float* __restrict__ m, int64
             }
         }
     };
-    constexpr int nq = kPT / kPTChunk;
+    // at least one chunk: a task always has a column
+    const int nq = (ncol + kPTChunk - 1) / kPTChunk;
+    int q = 0;
 #pragma nounroll
-    for (int q = 0; q < nq; ++q) {
-        const int c = q * kPTChunk;
-        math(ha, c, 0);
-        if (q + 1 < nq) {
+    do {
+        // the barriers keep each half-chunk's loads between the arithmetic
+        // of the two halves, in the order the waits above assume
+        const int cg = q * kPTChunk;
+        const int J = J0 + cg / kPT;
+        const int cb = cg % kPT;
+        const bool full = A < J;
+        math(ha, cb, 0, full);
+        asm volatile("" ::: "memory");
+        load4(cg + kPTChunk, ha);
+        asm volatile("" ::: "memory");
+        // the second half's values pass through here, so that its arithmetic
+        // (and the wait for its loads) stays after the loads just issued
 #pragma unroll
-            for (int s = 0; s < H; ++s)
-                ha[s] = *reinterpret_cast<const float4*>(rowp + (int64_t)(j0 + c + kPTChunk + s) * ld);
-        }
-        math(hb, c + H, H);
-        if (q + 1 < nq) {
+        for (int s = 0; s < H; ++s) asm volatile("" : "+v"(hb[s]));
+        math(hb, cb + H, H, full);
+        asm volatile("" ::: "memory");
+        load4(cg + kPTChunk + H, hb);
+        asm volatile("" ::: "memory");
+        strip_columns<MODE>(t, J, cb, min(kPT, k - J * kPT), cb + kPTChunk == kPT || q + 1 == nq, colx, coly, L);
+        // next column block: the positions of its columns
+        if (MODE == kPairStep && kStripGroup > 1) {
+            const bool nb = cb + kPTChunk == kPT;
 #pragma unroll
-            for (int s = 0; s < H; ++s)
-                hb[s] = *reinterpret_cast<const float4*>(rowp + (int64_t)(j0 + c + kPTChunk + H + s) * ld);
+            for (int b = 0; b + 1 < kStripGroup; ++b) {
+                xc[b].x = nb ? xc[b + 1].x : xc[b].x;
+                xc[b].y = nb ? xc[b + 1].y : xc[b].y;
+            }
+            xcol = xc[0];
         }
-        strip_columns<MODE, true>(t, q, px, py, L);
-    }
-    // rows 4 lane .. 4 lane + 3 of the strip are rows a .. a + 3 of block A
-    const int A = S * kStripBlocks + lane / 16;
-    const int64_t o = ((int64_t)A * T + J) * kPT + (4 * lane) % kPT;
-    *reinterpret_cast<float4*>(px + o) = make_float4(ax[0], ax[1], ax[2], ax[3]);
-    if (MODE == kPairStep) *reinterpret_cast<float4*>(py + o) = make_float4(ay[0], ay[1], ay[2], ay[3]);
+    } while (++q < nq);
+    // rows 4 lane .. 4 lane + 3 of the task are rows a .. a + 3 of block A
+    const int o = ((A * T + max(A, J0)) * kPT + (4 * lane) % kPT) * 4;
+    pend.off = A < T ? o : (int)kStripOutside;
+    pend.rx = t.prx;
+    pend.ry = t.pry;
+    pend.vx = StripU4{__float_as_uint(ax[0]), __float_as_uint(ax[1]), __float_as_uint(ax[2]), __float_as_uint(ax[3])};
+    pend.vy = StripU4{__float_as_uint(ay[0]), __float_as_uint(ay[1]), __float_as_uint(ay[2]), __float_as_uint(ay[3])};
 }
 
-template <int MODE, int NL, bool DIAG>
-__device__ __forceinline__ void strip_cols(const float* __restrict__ m, int64_t ld, int32_t k,
-                                           const float2* __restrict__ x, int S, int J, int T,
-                                           float* __restrict__ px, float* __restrict__ py, StripLds<MODE>& L) {
-    if ((J + 1) * kPT <= k)
-        strip_body<MODE, StripShape<NL, DIAG>, true>(m, ld, k, x, S, J, T, px, py, L);
-    else
-        strip_body<MODE, StripShape<NL, DIAG>, false>(m, ld, k, x, S, J, T, px, py, L);
-}
-
-// Dispatch on the strip's shape: NL = live row blocks (those below T and at
-// or left of J), DIAG = block J is one of them.
+// One task (S, J0).  MODE kPairStep: the position sums g (X_i - X_j) into
+// (px, py); kPairW: the weight sums w into px.  `m` is the subgraph's 1/Delta
+// block (k rows of ld floats, zero diagonal, rows zero-padded to ld), px and
+// py its partial blocks ([T][T][64] floats).  Stores the previous task's row
+// partials from `pend` and leaves this task's there.
 template <int MODE>
-__device__ __forceinline__ void strip(const float* __restrict__ m, int64_t ld, int32_t k,
-                                      const float2* __restrict__ x, int S, int J, int T, float* __restrict__ px,
-                                      float* __restrict__ py, StripLds<MODE>& L) {
-    const int d = J - kStripBlocks * S;
-    if (d >= kStripBlocks && (J + 1) * kPT <= k) {
-        strip_body_x4<MODE>(m, ld, k, x, S, J, T, px, py, L);
-        return;
-    }
-    const int nl = min(kStripBlocks, min(T - kStripBlocks * S, d + 1));
-    const bool diag = d < kStripBlocks;
-    switch (nl * 2 + (diag ? 1 : 0)) {
-        case 3: strip_cols<MODE, 1, true>(m, ld, k, x, S, J, T, px, py, L); break;
-        case 4: strip_cols<MODE, 2, false>(m, ld, k, x, S, J, T, px, py, L); break;
-        case 5: strip_cols<MODE, 2, true>(m, ld, k, x, S, J, T, px, py, L); break;
-        case 6: strip_cols<MODE, 3, false>(m, ld, k, x, S, J, T, px, py, L); break;
-        case 7: strip_cols<MODE, 3, true>(m, ld, k, x, S, J, T, px, py, L); break;
-        case 8: strip_cols<MODE, 4, false>(m, ld, k, x, S, J, T, px, py, L); break;
-        case 9: strip_cols<MODE, 4, true>(m, ld, k, x, S, J, T, px, py, L); break;
-        default: strip_cols<MODE, 1, false>(m, ld, k, x, S, J, T, px, py, L); break;
-    }
+__device__ __forceinline__ void strip_task(const float* __restrict__ m, int64_t ld, int32_t k,
+                                           const float2* __restrict__ x, int S, int J0, int T,
+                                           float* __restrict__ px, float* __restrict__ py, StripLds<MODE>& L,
+                                           StripPend& pend) {
+    const int nJ = min(kStripGroup, T - J0);
+    if (J0 >= kStripBlocks * S + kStripBlocks && (J0 + nJ) * kPT <= k)
+        strip_task_body<MODE, false>(m, ld, k, x, S, J0, T, px, py, L, pend);
+    else
+        strip_task_body<MODE, true>(m, ld, k, x, S, J0, T, px, py, L, pend);
 }
 
-// Node i (row block A) of a k-node subgraph: add its partial slots in a fixed
-// order, the column slots S < ceil(A / 4) and then the row slots J >= A.
-// MODE kPairW writes the weight sum; kPairStep writes
+// Node i (row block A, super-row S = A / 4) of a k-node subgraph: add its
+// partial slots in a fixed order, the column slots (A, S') for S' <
+// ceil(A / 4), then the row slots (A, A) and (A, 4 S + kStripGroup m) for
+// m >= 1.  MODE kPairW writes the weight sum; kPairStep writes
 // X+_i = X_i + sum_j g (X_i - X_j) / sum_j w (X_i when the weight sum is 0).
 template <int MODE>
 __device__ __forceinline__ void strip_finalize(int i, int T, const float* __restrict__ px,
@@ -596,7 +605,7 @@ __device__ __forceinline__ void strip_finalize(int i, int T, const float* __rest
         sx += px[o];
         if (MODE == kPairStep) sy += py[o];
     }
-    for (int B = A; B < T; ++B) {
+    for (int B = A; B < T; B = (B == A ? (A / kStripBlocks) * kStripBlocks + kStripGroup : B + kStripGroup)) {
         const int64_t o = base + (int64_t)B * kPT;
         sx += px[o];
         if (MODE == kPairStep) sy += py[o];
