@@ -129,3 +129,40 @@ def test_graph_plan_replays(setup):
             assert torch.equal(bufs2[k], ref[k]), (rep, k)
         _ = (bufs2["x_out"] * 2).sum().item()  # eager work between replays
     plan.close()
+
+
+def test_batch_sweep_task_queue():
+    # More layout tasks than the sweep launch has waves (4096 on 256 CUs at
+    # four 256-thread blocks each, 5120 at five), so that waves also take
+    # tasks from the launch's queue: 6000 small subgraphs (one task each) and
+    # a few large ones.  One batched sweep of every subgraph against the FP64
+    # Jacobi step on the batch's own Delta.
+    ops = get_ops()
+    rng = np.random.default_rng(23)
+    sizes = [int(v) for v in rng.integers(1, 65, 6000)] + [300, 700, 1153, 2048, 2304]
+    graphs = []
+    for i, n in enumerate(sizes):
+        nb = int(min(n, rng.integers(1, 5)))
+        graphs.append(synth.sbm(synth.equal_blocks(n, max(nb, 1)), 0.3, 0.02, 9000 + i))
+    gb = synth.concat_graphs(graphs)
+    b = ops.Batch(gb, "cuda")
+    x0 = torch.as_tensor(synth.uniform_layout(b.n_nodes, 29), device="cuda")
+    bufs = b.buffers(x0)
+    print(f"[batch queue] graphs={b.n_graphs} nodes={b.n_nodes} nnz={b.nnz}", flush=True)
+    ops.pprviz_batch(b, bufs, tol=1e-6, stress_iters=1)
+    torch.cuda.synchronize()
+    x0h = x0.double().cpu().numpy()
+    xo = bufs["x_out"].double().cpu().numpy()
+    delta = bufs["delta"].cpu().numpy()
+    for gi, g in enumerate(gb.graphs):
+        n = g.n
+        a = int(gb.node_off[gi])
+        X = x0h[a:a + n]
+        got = xo[a:a + n]
+        if n == 1:
+            np.testing.assert_array_equal(got, X)
+            continue
+        m = int(gb.mat_off[gi])
+        D = delta[m:m + n * n].reshape(n, n).astype(np.float64)
+        want = O.jacobi_step(X, D)
+        assert np.abs(got - want).max() <= STEP_REL * np.abs(want).max(), (gi, n)
