@@ -285,10 +285,10 @@ typedef unsigned int StripU4 __attribute__((ext_vector_type(4)));
 template <int N>
 constexpr int kWaitVmcnt = (N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8);
 
-// A strip's row partials, stored by the next strip of the same wave once
-// that strip's loads are in flight.  Loads and stores retire in one ordered
-// count, so a store issued at the end of a strip would hold up the first
-// wait of the next one until the write is acknowledged.
+// A task's row partials, stored by the next task of the same wave once that
+// task's loads are in flight.  Loads and stores retire in one ordered count,
+// so a store issued at the end of a task would hold up the first wait of the
+// next one until the write is acknowledged.
 struct StripPend {
     StripU4 vx, vy;
     __amdgpu_buffer_rsrc_t rx, ry;
