@@ -135,11 +135,14 @@ def test_batch_sweep_task_queue():
     # More layout tasks than the sweep launch has waves (4096 on 256 CUs at
     # four 256-thread blocks each, 5120 at five), so that waves also take
     # tasks from the launch's queue: 6000 small subgraphs (one task each) and
-    # a few large ones.  One batched sweep of every subgraph against the FP64
+    # 15 large ones.  One batched sweep of every subgraph against the FP64
     # Jacobi step on the batch's own Delta.
     ops = get_ops()
     rng = np.random.default_rng(23)
-    sizes = [int(v) for v in rng.integers(1, 65, 6000)] + [300, 700, 1153, 2048, 2304]
+    # the large ones sit on and around the 256-row super-row and 4-block task
+    # boundaries
+    sizes = [int(v) for v in rng.integers(1, 65, 6000)] + [255, 256, 257, 300, 511, 513, 700, 1023, 1153, 1280,
+                                                        1281, 1536, 1793, 2048, 2304]
     graphs = []
     for i, n in enumerate(sizes):
         nb = int(min(n, rng.integers(1, 5)))
